@@ -1,0 +1,175 @@
+/*
+ * eigupd.h -- C ABI of the MI355X rank-k symmetric eigen-update library
+ * (libeigupd.so, HIP kernels for gfx950).
+ *
+ * Method: Oh & Hu, "Multiple-rank Modification of Symmetric Eigenvalue
+ * Problem" (arXiv:1706.00773).  Given a resident decomposition
+ * A = Q diag(lambda) Q^T (Sec. 2.1) and a perturbation K Sigma K^T, K n-by-k,
+ * Sigma = diag(sigma_c) with sigma_c = +-1 (the paper's K K^T of Sec. 2.1 and
+ * the one-column-one-row form e_j a^T + a e_j^T of Sec. 2.2, Steps 1-2, which
+ * is k = 2, Sigma = diag(1, -1)), one update computes the eigen-decomposition
+ * of A' = A + K Sigma K^T:
+ *   U = Q^T K                                 (Sec. 2.1, below eq. (1))
+ *   all n roots of det(I_k - Sigma U^T (xI - diag(lambda))^{-1} U) = 0
+ *     (eq. (1)), located per pole interval by an inertia count that plays
+ *     the role of the modified Sturm chain (Sec. 2.2) and refined by
+ *     safeguarded Newton/bisection (the zero finder of Sec. 2.3)
+ *   eigenvectors w = (lambda' I - diag(lambda))^{-1} U c, normalised
+ *     (Sec. 2.4, eq. (10)), back-transformed Q' = Q W.
+ * Everything runs in FP64 on the device.
+ *
+ * Conventions common to all entry points
+ *   - Matrices are column-major.  lambda is ascending.
+ *   - A state is bound to one device for its lifetime and is not
+ *     thread-safe; distinct states may be used concurrently.
+ *   - `hip_stream` is a hipStream_t (NULL = the default stream).  Work is
+ *     enqueued on it in stream order.  Device pointers passed in are
+ *     borrowed until the stream reaches the work that reads them; host
+ *     pointers are copied before the call returns.
+ *   - Every entry point returns an eig_status code (EIG_OK = 0).  Argument
+ *     errors are reported synchronously and leave the state unchanged.
+ *     Errors detected on the device (non-finite input, non-convergence) are
+ *     deferred: they are sticky, every later update on the state becomes a
+ *     no-op on the device, and the next eig_query reports the first one,
+ *     clears it and leaves the state at its last committed decomposition.
+ */
+#ifndef EIGUPD_H
+#define EIGUPD_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct eig_state_s *eig_state_t;
+
+/* Per-update diagnostics returned by eig_query (values of the last update). */
+typedef struct {
+  int64_t n;                 /* order of the matrix */
+  int64_t k;                 /* rank of the last update */
+  int64_t p, q;              /* number of sigma_c = +1 and = -1 */
+  int64_t n_deflated_rows;   /* eigenpairs deflated (tiny rows of U, equal-pole groups) */
+  int64_t n_deflated_groups; /* near-equal pole groups of two or more rows */
+  int64_t n_segments;        /* distinct poles of the reduced secular problem */
+  int32_t iters_min;         /* count/Newton evaluations per root */
+  int32_t iters_max;
+  double iters_mean;
+  double defl_backward_err;  /* bound on ||perturbation|| introduced by deflation */
+  double anorm_bound;        /* max|lambda| + ||U||_F^2 >= ||A'||_2 */
+  int64_t generation;        /* updates committed since the last upload */
+  double ms[8];              /* phase times of the last update in milliseconds when it ran
+                                with EIG_PHASE_TIMING (else 0): [0] Q^T K, [1] deflation,
+                                [2] pole counts and location, [3] root refinement and null
+                                vectors, [4] eigenvalue merge and W, [5] Q W, [6] commit,
+                                [7] whole update */
+} eig_info;
+
+/* Status codes. */
+enum {
+  EIG_OK = 0,
+  EIG_EINVAL = -1,       /* invalid argument */
+  EIG_ENOMEM = -2,       /* device allocation failed */
+  EIG_EDEVICE = -3,      /* HIP runtime error or no such device */
+  EIG_ENOCONV = -4,      /* a root did not converge within the evaluation cap */
+  EIG_ENOTSORTED = -5,   /* uploaded lambda not ascending */
+  EIG_EUNSUPPORTED = -6, /* k beyond EIG_KMAX or a mode not built */
+  EIG_EDEPENDENCY = -7,  /* reserved: a predecessor update failed */
+  EIG_ESTATE = -8,       /* state not uploaded */
+  EIG_ENONFINITE = -9    /* NaN or Inf in an input or in U */
+};
+
+/* Mode bits of eig_update_rankk. */
+enum {
+  EIG_GEMM_FP64 = 0,        /* Q^T K and Q W in FP64 */
+  EIG_VALUES_ONLY = 1 << 4, /* eigenvalues only: nothing is committed, eig_query
+                               returns these values until the next update */
+  EIG_HOST_INPUT = 1 << 6,  /* K is a host pointer (copied before return) */
+  EIG_PHASE_TIMING = 1 << 7 /* record HIP events between the phases on hip_stream;
+                               eig_query reports the times in eig_info.ms */
+};
+
+enum { EIG_KMAX = 8 };
+
+/* Create a state for matrices of order n on HIP device `device`, and allocate
+ * all its device memory: two copies of (lambda, Q) used alternately, the
+ * n-by-n eigenvector matrix W and O(n * EIG_KMAX) of workspace -- about
+ * 24 n^2 bytes.  No later call allocates device memory.
+ * Errors: EIG_EINVAL (out NULL, n < 1), EIG_EDEVICE, EIG_ENOMEM.
+ * On success *out owns the memory until eig_state_destroy. */
+int eig_state_create(eig_state_t *out, int64_t n, int32_t device);
+
+/* Load a decomposition: lambda (n values, ascending, ties allowed) and Q
+ * (n-by-n column-major, leading dimension ldq >= n, columns orthonormal).
+ * ptrs_on_device != 0: both are device pointers on the state's device.
+ * The call synchronises `hip_stream`.  Resets the generation to 0 and clears
+ * any deferred error.  Errors: EIG_EINVAL, EIG_ENOTSORTED (lambda descends
+ * somewhere or is not finite), EIG_EDEVICE. */
+int eig_state_upload(eig_state_t s, const double *lambda, const double *Q, int64_t ldq,
+                     int32_t ptrs_on_device, void *hip_stream);
+
+/* Apply A' = A + K Sigma K^T to the resident decomposition (Sec. 2.1-2.4).
+ *   k      rank, 1 <= k <= min(n, EIG_KMAX)
+ *   K      n-by-k column-major, leading dimension ldk >= n; a device pointer
+ *          unless mode has EIG_HOST_INPUT
+ *   sigma  host array of k entries, each +1 or -1
+ *   mode   EIG_GEMM_FP64, optionally | EIG_VALUES_ONLY | EIG_HOST_INPUT
+ *          | EIG_PHASE_TIMING
+ * Asynchronous: enqueues the kernels on `hip_stream` and returns.  On the
+ * device the update writes the new pair into the state's other buffer and
+ * commits it only if no error was raised; the state then holds A'.
+ * Errors (synchronous): EIG_EINVAL, EIG_EUNSUPPORTED (k > EIG_KMAX),
+ * EIG_ESTATE (no upload yet), EIG_EDEVICE (launch failure).  Deferred:
+ * EIG_ENONFINITE, EIG_ENOCONV (see the file header). */
+int eig_update_rankk(eig_state_t s, int64_t k, const double *K, int64_t ldk,
+                     const int8_t *sigma, uint32_t mode, void *hip_stream);
+
+/* Synchronise `hip_stream`, report any deferred error, and copy out the
+ * committed decomposition: lambda_out (n values, ascending; may be NULL) and
+ * Q_out (n-by-n column-major, leading dimension ldq >= n; may be NULL).
+ * Columns of Q_out are unit eigenvectors; in the Q basis each one's
+ * component at its root's nearest pole is positive.  ptrs_on_device != 0:
+ * the outputs are device pointers.  info may be NULL.
+ * If the last update used EIG_VALUES_ONLY, lambda_out receives its values.
+ * Returns the deferred error if one was raised (outputs then hold the last
+ * committed decomposition), else EIG_OK. */
+int eig_query(eig_state_t s, double *lambda_out, double *Q_out, int64_t ldq,
+              int32_t ptrs_on_device, eig_info *info, void *hip_stream);
+
+/* Release all device memory of the state (after synchronising the device). */
+int eig_state_destroy(eig_state_t s);
+
+/* Static, human-readable text for a status code. */
+const char *eig_status_str(int status);
+
+/* Diagnostics: copy an intermediate of the last update to host memory `dst`
+ * (`bytes` available) after synchronising `hip_stream`.  `what`:
+ *   EIG_DBG_U            U = Q^T K, n-by-k row-major doubles
+ *   EIG_DBG_POLE_COUNT   nu at each distinct pole of the reduced problem,
+ *                        n_segments int32 (eigenvalues strictly below it)
+ *   EIG_DBG_SEG_START    first reduced row of each segment, n_segments+1 int32
+ *   EIG_DBG_REDUCED_D    poles of the reduced problem, n-n_deflated doubles
+ *   EIG_DBG_REDUCED_ROW  original row of each reduced row, int32
+ *   EIG_DBG_ROOT_ORIGIN  segment index of each root's origin pole, int32
+ *   EIG_DBG_ROOT_TAU     each root's offset from its origin pole, doubles
+ *   EIG_DBG_ROOT_ITERS   evaluations spent on each root, int32
+ *   EIG_DBG_W            the Q-basis eigenvector matrix, n-by-n doubles
+ * Errors: EIG_EINVAL (unknown `what`, dst NULL or too small). */
+enum {
+  EIG_DBG_U = 1,
+  EIG_DBG_POLE_COUNT = 2,
+  EIG_DBG_SEG_START = 3,
+  EIG_DBG_REDUCED_D = 4,
+  EIG_DBG_REDUCED_ROW = 5,
+  EIG_DBG_ROOT_ORIGIN = 6,
+  EIG_DBG_ROOT_TAU = 7,
+  EIG_DBG_ROOT_ITERS = 8,
+  EIG_DBG_W = 9
+};
+int eig_debug_fetch(eig_state_t s, int32_t what, void *dst, int64_t bytes, void *hip_stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* EIGUPD_H */

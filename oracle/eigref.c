@@ -258,21 +258,15 @@ int64_t eigref_count(int64_t n, int64_t k, const double *lam, const double *U,
  * T_j = sum_{l: lam_l != lam_j} u_l u_l^T / (lam_j - lam_l) - Sigma:
  *   nu(lam_j) = #{lam_l < lam_j} + neg(B_j) - p.
  * Requires every other row with lam_l == lam_j to be zero. */
-int64_t eigref_pole_count(int64_t n, int64_t k, const double *lam, const double *U,
-                          const int8_t *sigma, int64_t j) {
-  if (check_common(n, k, lam, U, sigma) != REF_OK || j < 0 || j >= n) return -2;
-  if (row_is_zero(k, U + j * k)) return -2;
+static int64_t pole_count_at(int64_t n, int64_t k, const double *lam, const double *U,
+                             const int8_t *sigma, int64_t j, double *B /* (k+1)^2 + k+1 */) {
   int64_t m = k + 1;
-  double *B = (double *)calloc((size_t)(m * m + m), sizeof(double));
-  if (!B) return -2;
+  for (int64_t a = 0; a < m * m; ++a) B[a] = 0.0;
   int64_t below = 0;
   for (int64_t l = 0; l < n; ++l) {
     if (lam[l] < lam[j]) ++below;
     if (lam[l] == lam[j]) {
-      if (l != j && !row_is_zero(k, U + l * k)) {
-        free(B);
-        return -2;
-      }
+      if (l != j && !row_is_zero(k, U + l * k)) return -2;
       continue;
     }
     double y = lam[j] - lam[l];
@@ -288,8 +282,19 @@ int64_t eigref_pole_count(int64_t n, int64_t k, const double *lam, const double 
   jacobi_sym((int)m, B, B + m * m, NULL);
   int64_t neg = 0;
   for (int64_t c = 0; c < m; ++c) neg += (B[m * m + c] < 0.0);
-  free(B);
   return below + neg - n_positive_sigma(k, sigma);
+}
+
+int64_t eigref_pole_count(int64_t n, int64_t k, const double *lam, const double *U,
+                          const int8_t *sigma, int64_t j) {
+  if (check_common(n, k, lam, U, sigma) != REF_OK || j < 0 || j >= n) return -2;
+  if (row_is_zero(k, U + j * k)) return -2;
+  int64_t m = k + 1;
+  double *B = (double *)calloc((size_t)(m * m + m), sizeof(double));
+  if (!B) return -2;
+  int64_t r = pole_count_at(n, k, lam, U, sigma, j, B);
+  free(B);
+  return r;
 }
 
 /* ------------------------------------------------------------------------ */
@@ -416,6 +421,31 @@ typedef struct {
 
 /* eigenvalue index i (0-based over all n eigenvalues): returns x = lam[*o] + *tau
  * (or x = *tau when *o < 0) and the number of count evaluations. */
+/* The bracket (lo, hi) has converged in absolute terms but an active pole lies
+ * strictly inside it: the root is within rounding of that pole.  If that pole
+ * value is unique among the active rows, decide the side of the root with the
+ * count at the pole and continue in coordinates centred on it (so that the
+ * distance to that pole, which eq. (10) divides by, is resolved to full
+ * relative precision).  Returns the pole index, or -1 (keep the absolute
+ * answer). */
+static int64_t onto_pole(const problem_t *P, int64_t target, double lo, double hi, double *tlo,
+                         double *thi, double *B) {
+  int64_t t = first_active_above(P->na, P->act, P->lam, lo);
+  if (t >= P->na || !(P->lam[P->act[t]] < hi)) return -1;
+  int64_t p = P->act[t];
+  if (t + 1 < P->na && P->lam[P->act[t + 1]] < hi) return -1; /* two poles inside */
+  int64_t c = pole_count_at(P->n, P->k, P->lam, P->U, P->sigma, p, B);
+  if (c < 0) return -1;
+  if (c >= target) { /* the root lies below the pole */
+    *tlo = lo - P->lam[p];
+    *thi = 0.0;
+  } else {
+    *tlo = 0.0;
+    *thi = hi - P->lam[p];
+  }
+  return p;
+}
+
 static int solve_one(const problem_t *P, int64_t i, int64_t *o_out, double *tau_out,
                      double *val_out, double *S, double *w) {
   const int64_t n = P->n, k = P->k;
@@ -425,23 +455,22 @@ static int solve_one(const problem_t *P, int64_t i, int64_t *o_out, double *tau_
   double lo = (i - P->q >= 0) ? lam[i - P->q] : P->lower;
   double hi = (i + P->p <= n - 1) ? lam[i + P->p] : P->upper;
   int evals = 0;
+  int64_t o = -1;
+  double tlo = 0.0, thi = 0.0;
   /* phase 1: absolute coordinates until no active pole lies strictly inside */
   for (;;) {
     int64_t t = first_active_above(P->na, P->act, lam, lo);
     int inside = (t < P->na && lam[P->act[t]] < hi);
     if (!inside) break;
-    if (hi - lo <= 2.0 * EPS * fmax(fabs(lo), fabs(hi))) {
+    double mid = lo + (hi - lo) / 2.0;
+    if (is_active_pole(P->na, P->act, lam, mid)) mid = nextafter(mid, hi);
+    if (hi - lo <= 2.0 * EPS * fmax(fabs(lo), fabs(hi)) || !(mid > lo && mid < hi) ||
+        is_active_pole(P->na, P->act, lam, mid)) {
+      o = onto_pole(P, target, lo, hi, &tlo, &thi, S);
+      if (o >= 0) goto shifted;
       *o_out = -1;
       *tau_out = lo + (hi - lo) / 2.0;
       *val_out = *tau_out;
-      return evals;
-    }
-    double mid = lo + (hi - lo) / 2.0;
-    if (is_active_pole(P->na, P->act, lam, mid)) mid = nextafter(mid, hi);
-    if (!(mid > lo && mid < hi) || is_active_pole(P->na, P->act, lam, mid)) {
-      *o_out = -1;
-      *tau_out = mid;
-      *val_out = mid;
       return evals;
     }
     int64_t c = count_below(n, k, lam, P->U, P->sigma, -1, mid, S, w);
@@ -456,7 +485,6 @@ static int solve_one(const problem_t *P, int64_t i, int64_t *o_out, double *tau_
   int64_t ia = (t > 0) ? P->act[t - 1] : -1; /* pole at or below lo */
   int64_t ib = (t < P->na) ? P->act[t] : -1;  /* pole at or above hi */
   if (ia >= 0 && lam[ia] > lo) ia = -1;
-  int64_t o;
   if (ia >= 0 && ib >= 0) {
     double a = lam[ia], b = lam[ib];
     double m = a + (b - a) / 2.0;
@@ -501,7 +529,9 @@ static int solve_one(const problem_t *P, int64_t i, int64_t *o_out, double *tau_
     return evals;
   }
   /* phase 2: bisection in shifted coordinates tau = x - lam[o] */
-  double tlo = lo - lam[o], thi = hi - lam[o];
+  tlo = lo - lam[o];
+  thi = hi - lam[o];
+shifted:
   for (;;) {
     if (thi - tlo <= 2.0 * EPS * fmax(fabs(tlo), fabs(thi))) break;
     double tm = tlo + (thi - tlo) / 2.0;
@@ -570,7 +600,7 @@ int eigref_eigvals(int64_t n, int64_t k, const double *lam, const double *U,
   int err = REF_OK;
 #pragma omp parallel
   {
-    double *S = (double *)malloc(sizeof(double) * (size_t)(k * k + k));
+    double *S = (double *)malloc(sizeof(double) * (size_t)((k + 1) * (k + 1) + (k + 1)));
     if (!S) {
 #pragma omp atomic write
       err = REF_ENOMEM;

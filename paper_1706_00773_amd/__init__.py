@@ -1,0 +1,274 @@
+"""MI355X rank-k symmetric eigen-update (Oh & Hu, arXiv:1706.00773).
+
+Thin ctypes binding of ``libeigupd.so`` (include/eigupd.h).  The functions
+keep the C names and only marshal arguments: every step of an update runs in
+the library's HIP kernels.  Torch tensors on the GPU are passed by device
+pointer (``data_ptr()``) together with torch's current HIP stream; numpy
+arrays are passed as host pointers.  Matrices are column-major: pass a numpy
+array in Fortran order or a torch tensor whose first stride is 1.
+
+If the library has not been built, the first call raises ``RuntimeError`` --
+there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libeigupd.so")
+
+EIG_OK = 0
+EIG_EINVAL = -1
+EIG_ENOMEM = -2
+EIG_EDEVICE = -3
+EIG_ENOCONV = -4
+EIG_ENOTSORTED = -5
+EIG_EUNSUPPORTED = -6
+EIG_EDEPENDENCY = -7
+EIG_ESTATE = -8
+EIG_ENONFINITE = -9
+
+EIG_GEMM_FP64 = 0
+EIG_VALUES_ONLY = 1 << 4
+EIG_HOST_INPUT = 1 << 6
+EIG_PHASE_TIMING = 1 << 7
+EIG_KMAX = 8
+
+EIG_DBG_U = 1
+EIG_DBG_POLE_COUNT = 2
+EIG_DBG_SEG_START = 3
+EIG_DBG_REDUCED_D = 4
+EIG_DBG_REDUCED_ROW = 5
+EIG_DBG_ROOT_ORIGIN = 6
+EIG_DBG_ROOT_TAU = 7
+EIG_DBG_ROOT_ITERS = 8
+EIG_DBG_W = 9
+
+EXPORTED = ("eig_state_create", "eig_state_upload", "eig_update_rankk", "eig_query",
+            "eig_state_destroy", "eig_status_str", "eig_debug_fetch")
+
+
+class eig_info(ctypes.Structure):
+    _fields_ = [
+        ("n", ctypes.c_int64),
+        ("k", ctypes.c_int64),
+        ("p", ctypes.c_int64),
+        ("q", ctypes.c_int64),
+        ("n_deflated_rows", ctypes.c_int64),
+        ("n_deflated_groups", ctypes.c_int64),
+        ("n_segments", ctypes.c_int64),
+        ("iters_min", ctypes.c_int32),
+        ("iters_max", ctypes.c_int32),
+        ("iters_mean", ctypes.c_double),
+        ("defl_backward_err", ctypes.c_double),
+        ("anorm_bound", ctypes.c_double),
+        ("generation", ctypes.c_int64),
+        ("ms", ctypes.c_double * 8),
+    ]
+
+    def as_dict(self):
+        return {f: (list(getattr(self, f)) if f == "ms" else getattr(self, f))
+                for f, _ in self._fields_}
+
+
+class EigError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        self.code = code
+        super().__init__(f"{where}: {eig_status_str(code)} ({code})")
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libeigupd.so and declare its C signatures (raises if it is missing)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(
+            f"{path} is missing: build it with `python -m paper_1706_00773_amd.build` "
+            "(there is no non-HIP fallback)")
+    lib = ctypes.CDLL(path)
+    vp, i64, i32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32
+    lib.eig_state_create.argtypes = [ctypes.POINTER(vp), i64, i32]
+    lib.eig_state_upload.argtypes = [vp, vp, vp, i64, i32, vp]
+    lib.eig_update_rankk.argtypes = [vp, i64, vp, i64, ctypes.POINTER(ctypes.c_int8),
+                                     ctypes.c_uint32, vp]
+    lib.eig_query.argtypes = [vp, vp, vp, i64, i32, ctypes.POINTER(eig_info), vp]
+    lib.eig_state_destroy.argtypes = [vp]
+    lib.eig_status_str.argtypes = [ctypes.c_int]
+    lib.eig_status_str.restype = ctypes.c_char_p
+    lib.eig_debug_fetch.argtypes = [vp, i32, vp, i64, vp]
+    for name in EXPORTED:
+        getattr(lib, name).restype = (ctypes.c_char_p if name == "eig_status_str"
+                                      else ctypes.c_int)
+    _lib = lib
+    return lib
+
+
+def eig_status_str(code: int) -> str:
+    return load_library().eig_status_str(int(code)).decode()
+
+
+def _check(rc: int, where: str) -> None:
+    if rc != EIG_OK:
+        raise EigError(rc, where)
+
+
+def _is_torch(x) -> bool:
+    return type(x).__module__.startswith("torch")
+
+
+def _current_stream(stream):
+    if stream is not None:
+        return stream if isinstance(stream, int) else stream.cuda_stream
+    import torch
+
+    return torch.cuda.current_stream().cuda_stream
+
+
+def _colmajor_ptr(a, n_rows: int):
+    """(pointer, leading dimension, on_device, keepalive) of a column-major matrix."""
+    if _is_torch(a):
+        import torch
+
+        if a.dtype != torch.float64:
+            raise TypeError("expected float64")
+        if a.dim() == 1:
+            return a.data_ptr(), max(n_rows, a.shape[0]), 1, a
+        if a.stride(0) != 1:
+            a = a.t().contiguous().t()
+        return a.data_ptr(), max(a.stride(1), n_rows), 1, a
+    a = np.asarray(a, dtype=np.float64)
+    if a.ndim == 1:
+        a = a.reshape(-1, 1)
+    a = np.asfortranarray(a)
+    return a.ctypes.data, a.shape[0], 0, a
+
+
+def eig_state_create(n: int, device: int = 0):
+    h = ctypes.c_void_p()
+    _check(load_library().eig_state_create(ctypes.byref(h), int(n), int(device)),
+           "eig_state_create")
+    return h
+
+
+def eig_state_destroy(s) -> None:
+    _check(load_library().eig_state_destroy(s), "eig_state_destroy")
+
+
+def eig_state_upload(s, lam, Q, stream=None) -> None:
+    """Load lambda (ascending) and Q (column-major); both torch-on-GPU or both numpy."""
+    n = lam.shape[0]
+    qp, ldq, qdev, qk = _colmajor_ptr(Q, n)
+    if _is_torch(lam):
+        lam_c = lam.contiguous()
+        lp, ldev = lam_c.data_ptr(), 1
+    else:
+        lam_c = np.ascontiguousarray(lam, dtype=np.float64)
+        lp, ldev = lam_c.ctypes.data, 0
+    if ldev != qdev:
+        raise ValueError("lambda and Q must both be device tensors or both host arrays")
+    st = _current_stream(stream) if qdev else None
+    _check(load_library().eig_state_upload(s, lp, qp, ldq, qdev, st), "eig_state_upload")
+
+
+def eig_update_rankk(s, K, sigma, mode: int = EIG_GEMM_FP64, stream=None) -> None:
+    """Enqueue A' = A + K diag(sigma) K^T.  K: n-by-k column-major (torch on the GPU, or
+    numpy on the host, which sets EIG_HOST_INPUT); sigma: k values of +-1."""
+    n = K.shape[0]
+    k = 1 if K.ndim == 1 else K.shape[1]
+    kp, ldk, kdev, keep = _colmajor_ptr(K, n)
+    if not kdev:
+        mode |= EIG_HOST_INPUT
+    sig = (ctypes.c_int8 * k)(*[int(v) for v in np.asarray(sigma).ravel()[:k]])
+    st = _current_stream(stream) if (kdev or stream is not None) else None
+    _check(load_library().eig_update_rankk(s, k, kp, ldk, sig, int(mode), st),
+           "eig_update_rankk")
+
+
+def eig_query(s, lambda_out=None, Q_out=None, stream=None, want_info: bool = True):
+    """Synchronise, raise on a deferred error, copy out the committed decomposition.
+
+    lambda_out / Q_out: torch tensors on the GPU (Q_out column-major) or numpy arrays
+    (Q_out in Fortran order), or None.  Returns an eig_info (or None)."""
+    lib = load_library()
+    lp = qp = None
+    ldq = 1
+    dev = None
+    if lambda_out is not None:
+        if _is_torch(lambda_out):
+            lp, dev = lambda_out.data_ptr(), 1
+        else:
+            if not (lambda_out.flags.c_contiguous and lambda_out.dtype == np.float64):
+                raise ValueError("lambda_out must be a contiguous float64 array")
+            lp, dev = lambda_out.ctypes.data, 0
+    if Q_out is not None:
+        if _is_torch(Q_out):
+            if Q_out.stride(0) != 1:
+                raise ValueError("Q_out must be column-major (stride(0) == 1)")
+            qp, ldq, qdev = Q_out.data_ptr(), Q_out.stride(1), 1
+        else:
+            if not (Q_out.flags.f_contiguous and Q_out.dtype == np.float64):
+                raise ValueError("Q_out must be a Fortran-ordered float64 array")
+            qp, ldq, qdev = Q_out.ctypes.data, Q_out.shape[0], 0
+        if dev is not None and dev != qdev:
+            raise ValueError("outputs must both be on the device or both on the host")
+        dev = qdev
+    info = eig_info() if want_info else None
+    st = _current_stream(stream) if (dev or stream is not None) else None
+    rc = lib.eig_query(s, lp, qp, max(ldq, 1), int(bool(dev)),
+                       ctypes.byref(info) if info is not None else None, st)
+    _check(rc, "eig_query")
+    return info
+
+
+def eig_debug_fetch(s, what: int, count: int, dtype, stream=None) -> np.ndarray:
+    out = np.empty(count, dtype=dtype)
+    st = _current_stream(stream) if stream is not None else None
+    _check(load_library().eig_debug_fetch(s, int(what), out.ctypes.data, out.nbytes, st),
+           "eig_debug_fetch")
+    return out
+
+
+class EigState:
+    """A resident decomposition on one GPU (owns an eig_state_t)."""
+
+    def __init__(self, n: int, device: int = 0):
+        self.n = int(n)
+        self.device = int(device)
+        self.handle = eig_state_create(self.n, self.device)
+
+    def upload(self, lam, Q, stream=None):
+        eig_state_upload(self.handle, lam, Q, stream)
+
+    def update(self, K, sigma, mode: int = EIG_GEMM_FP64, stream=None):
+        eig_update_rankk(self.handle, K, sigma, mode, stream)
+
+    def query(self, lambda_out=None, Q_out=None, stream=None):
+        return eig_query(self.handle, lambda_out, Q_out, stream)
+
+    def fetch(self, what: int, count: int, dtype=np.float64, stream=None):
+        return eig_debug_fetch(self.handle, what, count, dtype, stream)
+
+    def close(self):
+        if self.handle is not None:
+            eig_state_destroy(self.handle)
+            self.handle = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,396 @@
+// api.hip -- the C ABI of libeigupd (declared in include/eigupd.h): state
+// management, argument checks and the stream-ordered launch sequence of one
+// rank-k update.  All device memory is allocated once, in eig_state_create.
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <new>
+#include <vector>
+
+#include "eigupd.h"
+#include "internal.h"
+
+using namespace eigupd;
+
+struct eig_state_s {
+  int device = 0;
+  int64_t n = 0;
+  void* block = nullptr;
+  size_t block_bytes = 0;
+  double* lam[2] = {nullptr, nullptr};
+  double* Q[2] = {nullptr, nullptr};
+  double* lam_vo = nullptr;
+  double* Kbuf = nullptr;
+  Work w{};
+  hipEvent_t ev[9] = {};
+  bool timed = false;
+  int64_t enq_gen = 0;
+  bool uploaded = false;
+  bool last_vo = false;
+  int last_k = 0;
+};
+
+namespace {
+
+struct DeviceGuard {
+  int prev = -1;
+  bool ok = false;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+    ok = (hipSetDevice(dev) == hipSuccess);
+  }
+  ~DeviceGuard() {
+    if (prev >= 0) (void)hipSetDevice(prev);
+  }
+};
+
+struct Carver {
+  char* base;
+  size_t off = 0;
+  explicit Carver(void* b) : base(static_cast<char*>(b)) {}
+  template <typename T>
+  T* take(size_t count) {
+    off = (off + 255) & ~size_t(255);
+    T* p = base ? reinterpret_cast<T*>(base + off) : nullptr;
+    off += count * sizeof(T);
+    return p;
+  }
+};
+
+// Lays out every buffer of a state of order n inside `base` (nullptr: sizing pass).
+size_t carve(eig_state_s* s, void* base) {
+  const size_t n = (size_t)s->n;
+  Carver c(base);
+  s->lam[0] = c.take<double>(n);
+  s->lam[1] = c.take<double>(n);
+  s->lam_vo = c.take<double>(n);
+  s->Q[0] = c.take<double>(n * n);
+  s->Q[1] = c.take<double>(n * n);
+  Work& w = s->w;
+  w.W = c.take<double>(n * n);
+  s->Kbuf = c.take<double>(n * KMAX);
+  w.U = c.take<double>(n * KMAX);
+  w.tiny = c.take<int>(n);
+  w.nt_list = c.take<int>(n);
+  w.grp_id = c.take<int>(n);
+  w.g_first = c.take<int>(n);
+  w.g_m = c.take<int>(n);
+  w.g_r = c.take<int>(n);
+  w.g_h = c.take<int>(n);
+  w.g_val = c.take<double>(n);
+  w.hv = c.take<double>(n * KMAX);
+  w.hbeta = c.take<double>(n * KMAX);
+  w.urot = c.take<double>(n * KMAX);
+  w.mg_list = c.take<int>(n);
+  w.rd = c.take<double>(n);
+  w.ru = c.take<double>(n * KMAX);
+  w.rrow = c.take<int>(n);
+  w.rmap = c.take<int>(n);
+  w.row_seg = c.take<int>(n);
+  w.seg_start = c.take<int>(n + 1);
+  w.seg_r = c.take<int>(n);
+  w.dval = c.take<double>(n);
+  w.drow = c.take<int>(n);
+  w.nu = c.take<int>(n);
+  w.root_t = c.take<int>(n);
+  w.root_clo = c.take<int>(n);
+  w.root_chi = c.take<int>(n);
+  w.root_o = c.take<int>(n);
+  w.root_tau = c.take<double>(n);
+  w.root_c = c.take<double>(n * KMAX);
+  w.root_it = c.take<int>(n);
+  w.xs = c.take<double>(n);
+  w.colp = c.take<ColParam>(n);
+  w.st = c.take<DevState>(1);
+  w.info = c.take<DevInfo>(1);
+  return c.off + 256;
+}
+
+int status_from_bits(int bits) {
+  if (bits & ST_NONFINITE) return EIG_ENONFINITE;
+  if (bits & ST_NOCONV) return EIG_ENOCONV;
+  if (bits) return EIG_EDEVICE;
+  return EIG_OK;
+}
+
+#define HIPCHK(x)                                   \
+  do {                                              \
+    if ((x) != hipSuccess) return EIG_EDEVICE;      \
+  } while (0)
+
+}  // namespace
+
+extern "C" {
+
+const char* eig_status_str(int status) {
+  switch (status) {
+    case EIG_OK: return "ok";
+    case EIG_EINVAL: return "invalid argument";
+    case EIG_ENOMEM: return "out of device memory";
+    case EIG_EDEVICE: return "HIP device or runtime error";
+    case EIG_ENOCONV: return "a secular root did not converge";
+    case EIG_ENOTSORTED: return "eigenvalues not ascending";
+    case EIG_EUNSUPPORTED: return "unsupported rank or mode";
+    case EIG_EDEPENDENCY: return "a predecessor update failed";
+    case EIG_ESTATE: return "state has no decomposition (upload first)";
+    case EIG_ENONFINITE: return "non-finite value in the input";
+    default: return "unknown status";
+  }
+}
+
+int eig_state_create(eig_state_t* out, int64_t n, int32_t device) {
+  if (!out || n < 1 || n > (int64_t)1 << 30) return EIG_EINVAL;
+  *out = nullptr;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return EIG_EDEVICE;
+  DeviceGuard g(device);
+  if (!g.ok) return EIG_EDEVICE;
+  eig_state_s* s = new (std::nothrow) eig_state_s();
+  if (!s) return EIG_ENOMEM;
+  s->device = device;
+  s->n = n;
+  s->w.n = (int)n;
+  const size_t bytes = carve(s, nullptr);
+  void* block = nullptr;
+  if (hipMalloc(&block, bytes) != hipSuccess) {
+    delete s;
+    (void)hipGetLastError();
+    return EIG_ENOMEM;
+  }
+  s->block = block;
+  s->block_bytes = bytes;
+  carve(s, block);
+  for (auto& e : s->ev) {
+    if (hipEventCreate(&e) != hipSuccess) {
+      for (auto& f : s->ev)
+        if (f) (void)hipEventDestroy(f);
+      (void)hipFree(block);
+      delete s;
+      return EIG_EDEVICE;
+    }
+  }
+  DevState z{};
+  if (hipMemcpy(s->w.st, &z, sizeof(z), hipMemcpyHostToDevice) != hipSuccess) {
+    (void)hipFree(block);
+    delete s;
+    return EIG_EDEVICE;
+  }
+  *out = s;
+  return EIG_OK;
+}
+
+int eig_state_destroy(eig_state_t s) {
+  if (!s) return EIG_EINVAL;
+  {
+    DeviceGuard g(s->device);
+    (void)hipDeviceSynchronize();
+    for (auto& e : s->ev)
+      if (e) (void)hipEventDestroy(e);
+    if (s->block) (void)hipFree(s->block);
+  }
+  delete s;
+  return EIG_OK;
+}
+
+int eig_state_upload(eig_state_t s, const double* lambda, const double* Q, int64_t ldq,
+                     int32_t ptrs_on_device, void* hip_stream) {
+  if (!s || !lambda || !Q || ldq < s->n) return EIG_EINVAL;
+  DeviceGuard g(s->device);
+  if (!g.ok) return EIG_EDEVICE;
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  const size_t n = (size_t)s->n;
+  std::vector<double> h(n);
+  const hipMemcpyKind kind = ptrs_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+  if (ptrs_on_device) {
+    HIPCHK(hipMemcpyAsync(h.data(), lambda, n * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+  } else {
+    memcpy(h.data(), lambda, n * sizeof(double));
+  }
+  for (size_t j = 0; j < n; ++j) {
+    if (!isfinite(h[j])) return EIG_ENOTSORTED;
+    if (j > 0 && !(h[j] >= h[j - 1])) return EIG_ENOTSORTED;
+  }
+  HIPCHK(hipMemcpyAsync(s->lam[0], h.data(), n * sizeof(double), hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpy2DAsync(s->Q[0], n * sizeof(double), Q, (size_t)ldq * sizeof(double),
+                          n * sizeof(double), n, kind, st));
+  DevState z{};
+  HIPCHK(hipMemcpyAsync(s->w.st, &z, sizeof(z), hipMemcpyHostToDevice, st));
+  HIPCHK(hipStreamSynchronize(st));
+  s->enq_gen = 0;
+  s->uploaded = true;
+  s->last_vo = false;
+  return EIG_OK;
+}
+
+int eig_update_rankk(eig_state_t s, int64_t k, const double* K, int64_t ldk, const int8_t* sigma,
+                     uint32_t mode, void* hip_stream) {
+  if (!s || !K || !sigma || k < 1 || ldk < s->n) return EIG_EINVAL;
+  if (k > EIG_KMAX) return EIG_EUNSUPPORTED;
+  if (k > s->n) return EIG_EINVAL;
+  const uint32_t known = EIG_VALUES_ONLY | EIG_HOST_INPUT | EIG_PHASE_TIMING;
+  if (mode & ~known) return EIG_EUNSUPPORTED;
+  int mask = 0;
+  for (int64_t c = 0; c < k; ++c) {
+    if (sigma[c] == 1)
+      mask |= 1 << c;
+    else if (sigma[c] != -1)
+      return EIG_EINVAL;
+  }
+  if (!s->uploaded) return EIG_ESTATE;
+  DeviceGuard g(s->device);
+  if (!g.ok) return EIG_EDEVICE;
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  const size_t n = (size_t)s->n;
+  Work w = s->w;
+  w.k = (int)k;
+  w.sig_pos_mask = mask;
+  if (mode & EIG_HOST_INPUT) {
+    HIPCHK(hipMemcpy2DAsync(s->Kbuf, n * sizeof(double), K, (size_t)ldk * sizeof(double),
+                            n * sizeof(double), (size_t)k, hipMemcpyHostToDevice, st));
+    HIPCHK(hipStreamSynchronize(st));
+    w.K = s->Kbuf;
+    w.ldk = (int)n;
+  } else {
+    w.K = K;
+    w.ldk = (int)ldk;
+  }
+  const int cur = (int)(s->enq_gen & 1);
+  w.lam_in = s->lam[cur];
+  w.Q_in = s->Q[cur];
+  w.lam_out = s->lam[cur ^ 1];
+  w.Q_out = s->Q[cur ^ 1];
+  const bool timed = (mode & EIG_PHASE_TIMING) != 0;
+  auto mark = [&](int i) -> hipError_t {
+    return timed ? hipEventRecord(s->ev[i], st) : hipSuccess;
+  };
+  const bool vo = (mode & EIG_VALUES_ONLY) != 0;
+  HIPCHK(mark(0));
+  HIPCHK(launch_qtk(w, st));
+  HIPCHK(mark(1));
+  HIPCHK(launch_deflate(w, st));
+  HIPCHK(mark(2));
+  HIPCHK(launch_polecount(w, st));
+  HIPCHK(launch_locate(w, st));
+  HIPCHK(mark(3));
+  HIPCHK(launch_rootsolve(w, st));
+  HIPCHK(mark(4));
+  s->last_k = (int)k;
+  s->timed = timed;
+  if (vo) {
+    HIPCHK(launch_finalize(w, s->lam_vo, st));
+    HIPCHK(mark(5));
+    HIPCHK(mark(6));
+    HIPCHK(mark(7));
+    HIPCHK(mark(8));
+    s->last_vo = true;
+    return EIG_OK;
+  }
+  HIPCHK(launch_finalize(w, w.lam_out, st));
+  HIPCHK(launch_wbuild(w, st));
+  HIPCHK(launch_group_reflect(w, st));
+  HIPCHK(mark(5));
+  HIPCHK(launch_dgemm((int)n, (int)n, (int)n, w.Q_in, (int)n, w.W, (int)n, w.Q_out, (int)n,
+                      &w.st->status, st));
+  HIPCHK(mark(6));
+  HIPCHK(launch_commit(w, st));
+  HIPCHK(mark(7));
+  HIPCHK(mark(8));
+  s->enq_gen += 1;
+  s->last_vo = false;
+  return EIG_OK;
+}
+
+int eig_query(eig_state_t s, double* lambda_out, double* Q_out, int64_t ldq,
+              int32_t ptrs_on_device, eig_info* info, void* hip_stream) {
+  if (!s) return EIG_EINVAL;
+  if (Q_out && ldq < s->n) return EIG_EINVAL;
+  DeviceGuard g(s->device);
+  if (!g.ok) return EIG_EDEVICE;
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  HIPCHK(hipStreamSynchronize(st));
+  DevState ds;
+  DevInfo di;
+  HIPCHK(hipMemcpy(&ds, s->w.st, sizeof(ds), hipMemcpyDeviceToHost));
+  HIPCHK(hipMemcpy(&di, s->w.info, sizeof(di), hipMemcpyDeviceToHost));
+  int rc = EIG_OK;
+  if (ds.status != 0) {
+    rc = status_from_bits(ds.status);
+    DevState z = ds;
+    z.status = 0;
+    HIPCHK(hipMemcpy(s->w.st, &z, sizeof(z), hipMemcpyHostToDevice));
+    s->enq_gen = ds.gen;
+    s->last_vo = false;
+  }
+  const size_t n = (size_t)s->n;
+  const int cur = (int)(ds.gen & 1);
+  const hipMemcpyKind kind = ptrs_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+  if (lambda_out && s->uploaded) {
+    const double* src = s->last_vo ? s->lam_vo : s->lam[cur];
+    HIPCHK(hipMemcpyAsync(lambda_out, src, n * sizeof(double), kind, st));
+  }
+  if (Q_out && s->uploaded) {
+    HIPCHK(hipMemcpy2DAsync(Q_out, (size_t)ldq * sizeof(double), s->Q[cur], n * sizeof(double),
+                            n * sizeof(double), n, kind, st));
+  }
+  HIPCHK(hipStreamSynchronize(st));
+  if (info) {
+    memset(info, 0, sizeof(*info));
+    info->n = s->n;
+    info->k = s->last_k;
+    if (s->last_k > 0) {
+      info->p = di.p;
+      info->q = di.q;
+      info->n_deflated_rows = di.n_defl;
+      info->n_deflated_groups = di.n_groups;
+      info->n_segments = di.n_s;
+      info->iters_min = (di.n_d > 0) ? di.it_min : 0;
+      info->iters_max = di.it_max;
+      info->iters_mean = (di.n_d > 0) ? (double)di.it_sum / (double)di.n_d : 0.0;
+      info->defl_backward_err = di.bwd;
+      info->anorm_bound = di.ahat;
+    }
+    info->generation = ds.gen;
+    if (s->timed) {
+      for (int i = 0; i < 7; ++i) {
+        float ms = 0.0f;
+        if (hipEventElapsedTime(&ms, s->ev[i], s->ev[i + 1]) == hipSuccess) info->ms[i] = ms;
+      }
+      float tot = 0.0f;
+      if (hipEventElapsedTime(&tot, s->ev[0], s->ev[8]) == hipSuccess) info->ms[7] = tot;
+    }
+  }
+  return rc;
+}
+
+int eig_debug_fetch(eig_state_t s, int32_t what, void* dst, int64_t bytes, void* hip_stream) {
+  if (!s || !dst || bytes < 0) return EIG_EINVAL;
+  DeviceGuard g(s->device);
+  if (!g.ok) return EIG_EDEVICE;
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  HIPCHK(hipStreamSynchronize(st));
+  DevInfo di;
+  HIPCHK(hipMemcpy(&di, s->w.info, sizeof(di), hipMemcpyDeviceToHost));
+  const size_t n = (size_t)s->n;
+  const Work& w = s->w;
+  const void* src = nullptr;
+  size_t need = 0;
+  switch (what) {
+    case EIG_DBG_U: src = w.U; need = n * (size_t)s->last_k * sizeof(double); break;
+    case EIG_DBG_POLE_COUNT: src = w.nu; need = (size_t)di.n_s * sizeof(int); break;
+    case EIG_DBG_SEG_START: src = w.seg_start; need = (size_t)(di.n_s + 1) * sizeof(int); break;
+    case EIG_DBG_REDUCED_D: src = w.rd; need = (size_t)di.n_d * sizeof(double); break;
+    case EIG_DBG_REDUCED_ROW: src = w.rrow; need = (size_t)di.n_d * sizeof(int); break;
+    case EIG_DBG_ROOT_ORIGIN: src = w.root_o; need = (size_t)di.n_d * sizeof(int); break;
+    case EIG_DBG_ROOT_TAU: src = w.root_tau; need = (size_t)di.n_d * sizeof(double); break;
+    case EIG_DBG_ROOT_ITERS: src = w.root_it; need = (size_t)di.n_d * sizeof(int); break;
+    case EIG_DBG_W: src = w.W; need = n * n * sizeof(double); break;
+    default: return EIG_EINVAL;
+  }
+  if ((size_t)bytes < need) return EIG_EINVAL;
+  if (need > 0) HIPCHK(hipMemcpy(dst, src, need, hipMemcpyDeviceToHost));
+  return EIG_OK;
+}
+
+}  // extern "C"

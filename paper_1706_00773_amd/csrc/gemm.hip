@@ -1,0 +1,162 @@
+// gemm.hip -- C = A B in FP64 on the CDNA4 matrix cores (the back-transform
+// Q' = Q W of Sec. 2.4, eq. (10): 2 n^3 flops, the dominant step).
+//
+// v_mfma_f64_16x16x4_f64: per wave, A fragment 16x4 (lane l holds A[l%16][l/16]),
+// B fragment 4x16 (lane l holds B[l/16][l%16]), accumulator 16x16 (lane l holds
+// rows l/16 + 4v, v = 0..3, of column l%16).
+//
+// Tiling: 128x128 block tile, 16-deep k slices, 256 threads = 4 waves in a 2x2
+// arrangement, each wave a 64x64 sub-tile = 4x4 MFMA tiles (64 doubles of
+// accumulator per lane).  Slices are staged global -> registers -> LDS with
+// double buffering: the next slice's global loads are in flight while the MFMAs
+// consume the current one, one barrier per slice.  Block ids are remapped so
+// that the blocks resident on one XCD (blocks are dealt round-robin to the 8
+// XCDs) cover one compact group of 8 tile rows, sharing its A panel and the B
+// panels in that XCD's L2.
+#include "common.h"
+
+namespace eigupd {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+constexpr int GBM = 128, GBN = 128, GBK = 16, GPAD = 4, GNT = 256;
+constexpr int GGROUP = 8;
+
+__device__ __forceinline__ void tile_of(int bid, int tiles_m, int tiles_n, int* tm, int* tn) {
+  const int total = tiles_m * tiles_n;
+  const int per = total / 8, rem = total % 8;
+  const int x = bid % 8, local = bid / 8;
+  const int tile = (x < rem ? x * (per + 1) : rem * (per + 1) + (x - rem) * per) + local;
+  const int tpg = GGROUP * tiles_n;
+  const int group = tile / tpg;
+  const int first_m = group * GGROUP;
+  const int gsz = min(tiles_m - first_m, GGROUP);
+  const int in = tile % tpg;
+  *tm = first_m + in % gsz;
+  *tn = in / gsz;
+}
+
+__global__ __launch_bounds__(GNT, 2) void dgemm_kernel(int M, int N, int Kd,
+                                                       const double* __restrict__ A, int lda,
+                                                       const double* __restrict__ B, int ldb,
+                                                       double* __restrict__ C, int ldc,
+                                                       const int32_t* status, int tiles_m,
+                                                       int tiles_n, int vec) {
+  if (__builtin_nontemporal_load(status) != 0) return;
+  __shared__ double As[2][GBK][GBM + GPAD];
+  __shared__ double Bs[2][GBK][GBN + GPAD];
+  int tm, tn;
+  tile_of(blockIdx.x, tiles_m, tiles_n, &tm, &tn);
+  const int m0 = tm * GBM, n0 = tn * GBN;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int wm = (wv & 1) * 64, wn = (wv >> 1) * 64;
+  // global load assignment
+  const int a_k = tid >> 4, a_m = (tid & 15) * 8;  // A: column k0+a_k, rows m0+a_m .. +8
+  const int b_n = tid >> 1, b_k = (tid & 1) * 8;   // B: column n0+b_n, rows k0+b_k .. +8
+  const bool full_m = vec && (m0 + GBM <= M), full_n = vec && (n0 + GBN <= N);
+  double ra[8], rb[8];
+
+  auto gload = [&](int k0) {
+    const bool full_k = (k0 + GBK <= Kd);
+    const int ka = k0 + a_k;
+    if (full_m && full_k) {
+      const double2* src = reinterpret_cast<const double2*>(A + (size_t)ka * lda + m0 + a_m);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const double2 v = src[q];
+        ra[2 * q] = v.x;
+        ra[2 * q + 1] = v.y;
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const int r = m0 + a_m + q;
+        ra[q] = (r < M && ka < Kd) ? A[(size_t)ka * lda + r] : 0.0;
+      }
+    }
+    const int nb = n0 + b_n;
+    if (full_n && full_k) {
+      const double2* src = reinterpret_cast<const double2*>(B + (size_t)nb * ldb + k0 + b_k);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const double2 v = src[q];
+        rb[2 * q] = v.x;
+        rb[2 * q + 1] = v.y;
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const int kk = k0 + b_k + q;
+        rb[q] = (nb < N && kk < Kd) ? B[(size_t)nb * ldb + kk] : 0.0;
+      }
+    }
+  };
+  auto sstore = [&](int buf) {
+#pragma unroll
+    for (int q = 0; q < 8; ++q) As[buf][a_k][a_m + q] = ra[q];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) Bs[buf][b_k + q][b_n] = rb[q];
+  };
+
+  d4 acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+
+  const int nk = (Kd + GBK - 1) / GBK;
+  gload(0);
+  sstore(0);
+  __syncthreads();
+  const int fr = lane & 15, fk = lane >> 4;
+  for (int kt = 0; kt < nk; ++kt) {
+    const int cur = kt & 1;
+    if (kt + 1 < nk) gload((kt + 1) * GBK);
+#pragma unroll
+    for (int ks = 0; ks < GBK / 4; ++ks) {
+      const int kr = ks * 4 + fk;
+      double a[4], b[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) a[i] = As[cur][kr][wm + i * 16 + fr];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) b[j] = Bs[cur][kr][wn + j * 16 + fr];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
+    }
+    if (kt + 1 < nk) sstore(cur ^ 1);
+    __syncthreads();
+  }
+  // epilogue: lane holds rows l/16 + 4v of column l%16 of each 16x16 tile; for a
+  // fixed v the wave writes 4 consecutive rows of 16 columns
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int col = n0 + wn + j * 16 + fr;
+      if (col < N) {
+        double* dst = C + (size_t)col * ldc;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int row = m0 + wm + i * 16 + fk + 4 * v;
+          if (row < M) dst[row] = acc[i][j][v];
+        }
+      }
+    }
+}
+
+hipError_t launch_dgemm(int M, int N, int Kd, const double* A, int lda, const double* B, int ldb,
+                        double* C, int ldc, const int32_t* status, hipStream_t s) {
+  if (M <= 0 || N <= 0) return hipSuccess;
+  // 16-byte vector loads and stores need every column start 16-byte aligned
+  const int vec = !((lda & 1) || (ldb & 1) || (ldc & 1) || ((uintptr_t)A & 15) ||
+                    ((uintptr_t)B & 15) || ((uintptr_t)C & 15));
+  const int tiles_m = (M + GBM - 1) / GBM, tiles_n = (N + GBN - 1) / GBN;
+  hipLaunchKernelGGL(dgemm_kernel, dim3(tiles_m * tiles_n), dim3(GNT), 0, s, M, N, Kd, A, lda,
+                     B, ldb, C, ldc, status, tiles_m, tiles_n, vec);
+  return hipGetLastError();
+}
+
+}  // namespace eigupd

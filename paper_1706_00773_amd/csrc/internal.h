@@ -1,0 +1,120 @@
+// internal.h -- shared declarations of the HIP translation units of libeigupd.
+//
+// Data layout in device memory (n = order, K = compile-time rank bound):
+//   lam[2], Q[2]     two resident copies of (lambda, Q); an update reads one and
+//                    writes the other, the commit flips which one is current
+//   U                Q^T K, n rows of k doubles (row j = u_j, contiguous)
+//   reduced problem  rd (poles), ru (rows, k doubles each), rrow (original row
+//                    of each reduced row), rmap (original row -> reduced row or -1)
+//   segments         distinct poles: seg_start (first reduced row), seg_r (rows)
+//   deflated         dval (eigenvalue), drow (row of its unit vector)
+//   roots            root_o (origin segment), root_tau (offset), root_c (k doubles:
+//                    null vector scaled so that the eigenvector has unit norm)
+//   colparam         per output column: origin pole, tau, signed c, or a unit row
+//   W                n-by-n column-major eigenvectors in the Q basis
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace eigupd {
+
+constexpr int KMAX = 8;
+
+// Deferred error bits (DevState::status)
+constexpr int ST_NONFINITE = 1;
+constexpr int ST_NOCONV = 2;
+constexpr int ST_INTERNAL = 4;
+
+// Deflation thresholds, relative to ahat = max|lambda| + ||U||_F^2 (>= ||A'||_2):
+// a row u_j is dropped when ||u_j|| ||U||_F <= TAU_ROW * ahat; neighbouring poles
+// closer than TAU_GAP * ahat are merged into one group.
+constexpr double TAU_ROW = 1e-12;
+constexpr double TAU_GAP = 8.0 * 1.1102230246251565e-16;
+
+// Iteration cap per root (count and Newton evaluations together).
+constexpr int MAX_EVALS = 160;
+
+struct DevState {   // persistent for the life of a state
+  int32_t status;   // sticky error bits
+  int32_t pad;
+  long long gen;    // committed updates since upload
+};
+
+struct DevInfo {    // written by the kernels of one update
+  int32_t n_d, n_s, n_defl, n_groups;
+  int32_t p, q, k, n_nt;
+  double ahat, fro2, lower, upper, bwd;
+  int32_t it_min, it_max;
+  long long it_sum;
+};
+
+struct ColParam {   // one output column of W
+  double d_o;       // origin pole value (root columns)
+  double tau;       // offset of the root from d_o
+  double c[KMAX];   // signed, scaled null vector
+  int32_t drow;     // >= 0: unit vector e_drow (deflated column); -1: root column
+  int32_t pad;
+};
+
+struct Work {
+  int n, k, ldk, sig_pos_mask;  // bit c of sig_pos_mask set <=> sigma_c = +1
+  const double* lam_in;
+  const double* Q_in;
+  double* lam_out;
+  double* Q_out;
+  const double* K;
+  double* U;
+  // deflation
+  int* tiny;        // n   row flags
+  int* nt_list;     // n   non-tiny rows in order
+  int* grp_id;      // n   group of each non-tiny position
+  int* g_first;     // n   first non-tiny position of each group
+  int* g_m;         // n   group size
+  int* g_r;         // n   kept rows of each group
+  int* g_h;         // n   reflectors of each group
+  double* g_val;    // n   pole value of each group
+  double* hv;       // n*KMAX reflector vectors (by non-tiny position)
+  double* hbeta;    // n*KMAX reflector scalars (by group)
+  double* urot;     // n*KMAX rotated rows (by non-tiny position)
+  int* mg_list;     // n   groups with two or more rows
+  double* rd;       // n
+  double* ru;       // n*KMAX
+  int* rrow;        // n
+  int* rmap;        // n
+  int* row_seg;     // n   segment of each reduced row
+  int* seg_start;   // n+1
+  int* seg_r;       // n
+  double* dval;     // n
+  int* drow;        // n
+  // location and roots
+  int* nu;          // n   pole counts
+  int* root_t;      // n   interval of each root
+  int* root_clo;    // n   count at the interval's left end
+  int* root_chi;    // n   count at the interval's right end
+  int* root_o;      // n   origin segment
+  double* root_tau; // n
+  double* root_c;   // n*KMAX
+  int* root_it;     // n
+  double* xs;       // n   absolute root values (monotone)
+  ColParam* colp;   // n
+  double* W;        // n*n
+  DevState* st;
+  DevInfo* info;
+};
+
+// Launchers (stream-ordered, no allocation).
+hipError_t launch_qtk(const Work& w, hipStream_t s);
+hipError_t launch_deflate(const Work& w, hipStream_t s);
+hipError_t launch_polecount(const Work& w, hipStream_t s);
+hipError_t launch_locate(const Work& w, hipStream_t s);
+hipError_t launch_rootsolve(const Work& w, hipStream_t s);
+hipError_t launch_finalize(const Work& w, double* lam_dst, hipStream_t s);
+hipError_t launch_wbuild(const Work& w, hipStream_t s);
+hipError_t launch_group_reflect(const Work& w, hipStream_t s);
+hipError_t launch_commit(const Work& w, hipStream_t s);
+// C = A * B, column-major, FP64 MFMA.  Skipped on the device when *status != 0.
+hipError_t launch_dgemm(int M, int N, int Kd, const double* A, int lda, const double* B, int ldb,
+                        double* C, int ldc, const int32_t* status, hipStream_t s);
+
+}  // namespace eigupd

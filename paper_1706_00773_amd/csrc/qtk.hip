@@ -1,0 +1,80 @@
+// qtk.hip -- U = Q^T K (Sec. 2.1: U = Q^T K; Sec. 2.4 calls it L).
+//
+// Q is n-by-n column-major and K n-by-k with k <= 8, so U is a skinny product
+// bound by streaming Q from HBM once (8 n^2 bytes, 2 n^2 k flops).  A block of
+// 256 threads owns CPB consecutive columns of Q: each thread walks rows
+// r = tid, tid + 256, ... (coalesced along the column), keeps K's row r in
+// registers for all CPB columns, and the block reduces CPB*k partial sums at
+// the end.  Non-finite entries of U raise the sticky ST_NONFINITE bit.
+#include "common.h"
+
+namespace eigupd {
+
+template <int K, int CPB>
+__global__ __launch_bounds__(256) void qtk_kernel(Work w) {
+  if (update_cancelled(w.st)) return;
+  const int n = w.n;
+  const int j0 = blockIdx.x * CPB;
+  double acc[CPB][K];
+#pragma unroll
+  for (int q = 0; q < CPB; ++q)
+#pragma unroll
+    for (int c = 0; c < K; ++c) acc[q][c] = 0.0;
+  const double* __restrict__ Q = w.Q_in;
+  const double* __restrict__ Km = w.K;
+  const int ncol = min(CPB, n - j0);
+  for (int r = threadIdx.x; r < n; r += 256) {
+    double kr[K];
+#pragma unroll
+    for (int c = 0; c < K; ++c) kr[c] = Km[r + (size_t)c * w.ldk];
+#pragma unroll
+    for (int q = 0; q < CPB; ++q) {
+      const double v = (q < ncol) ? Q[r + (size_t)(j0 + q) * n] : 0.0;
+#pragma unroll
+      for (int c = 0; c < K; ++c) acc[q][c] = fma(v, kr[c], acc[q][c]);
+    }
+  }
+  __shared__ double red[4][CPB * K];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int q = 0; q < CPB; ++q)
+#pragma unroll
+    for (int c = 0; c < K; ++c) {
+      const double s = wave_sum(acc[q][c]);
+      if (lane == 0) red[wv][q * K + c] = s;
+    }
+  __syncthreads();
+  if (threadIdx.x < CPB * K) {
+    const int e = threadIdx.x;
+    const double s = red[0][e] + red[1][e] + red[2][e] + red[3][e];
+    const int q = e / K, c = e % K;
+    if (q < ncol) {
+      w.U[(size_t)(j0 + q) * K + c] = s;
+      if (!isfinite(s)) atomicOr(&w.st->status, ST_NONFINITE);
+    }
+  }
+}
+
+template <int K>
+static hipError_t qtk_launch(const Work& w, hipStream_t s) {
+  constexpr int CPB = (K <= 2) ? 8 : 4;
+  const int grid = (w.n + CPB - 1) / CPB;
+  hipLaunchKernelGGL((qtk_kernel<K, CPB>), dim3(grid), dim3(256), 0, s, w);
+  return hipGetLastError();
+}
+
+hipError_t launch_qtk(const Work& w, hipStream_t s) {
+  switch (w.k) {
+    case 1: return qtk_launch<1>(w, s);
+    case 2: return qtk_launch<2>(w, s);
+    case 3: return qtk_launch<3>(w, s);
+    case 4: return qtk_launch<4>(w, s);
+    case 5: return qtk_launch<5>(w, s);
+    case 6: return qtk_launch<6>(w, s);
+    case 7: return qtk_launch<7>(w, s);
+    case 8: return qtk_launch<8>(w, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace eigupd

@@ -1,0 +1,673 @@
+// secular.hip -- location and refinement of the roots of the multiple-rank
+// secular equation det(I - Sigma U^T (xI - D)^{-1} U) = 0 (Sec. 2.1, eq. (1)).
+//
+// Counting.  For x not a pole, the number of eigenvalues of D + U Sigma U^T
+// strictly below x is
+//     nu(x) = #{d_j < x} + neg(S(x)) - p,    S(x) = sum_j u_j u_j^T / (x - d_j) - Sigma,
+// (inertia of the bordered matrix [[D - xI, U], [U^T, -Sigma]] taken two
+// ways).  It is the integer that the paper's modified Sturm chain yields
+// (Sec. 2.2) but needs only a k-by-k inertia.  At a pole d_s with rows Y_s:
+//     nu(d_s) = #{d_j < d_s} + r_s + neg(P^T T_s P) - p,
+// T_s = sum_{j not in s} u_j u_j^T / (d_s - d_j) - Sigma, P an orthonormal
+// basis of the complement of the row space of Y_s.  The pole counts give the
+// location vector of Sec. 2.2 for any rank: interval t holds
+// nu(d_t) - nu(d_{t-1}) roots.
+//
+// Refinement.  Each root is solved in shifted coordinates x = d_o + tau around
+// the nearer pole of its interval; every difference x - d_j is formed as
+// tau - (d_j - d_o).  Between poles every eigenvalue branch of S(x) is
+// decreasing (S' = -sum u_j u_j^T / (x - d_j)^2), so a root is a simple zero of
+// g(x) = (x - d_a)^{r_a} (x - d_b)^{r_b} det S(x), which is smooth on the whole
+// interval [d_a, d_b].  Newton steps on g, d log g / dx = r_a/(x - d_a) +
+// r_b/(x - d_b) + tr(S^{-1} S'), are taken inside a bracket kept by the count;
+// a step that leaves the bracket or does not halve is replaced by bisection
+// (the zero finder of Sec. 2.3 with the count deciding the side).  Two or more
+// roots in one interval are first separated by count bisection.
+//
+// Kernel shape.  A block owns RPB roots and WV waves; each wave sums S and S'
+// over its slice of the poles for all RPB roots, with the 64/RPB parts of the
+// wave taking alternate poles of the slice.  The slice is streamed through a
+// per-wave LDS tile (coalesced loads, prefetched one tile ahead into
+// registers) and every lane of a part reads the same pole (an LDS broadcast).
+// Partial sums meet in LDS, and wave 0 does the k-by-k work (Jacobi
+// eigen-decomposition: inertia, Newton step, null vector) and writes the next
+// points.
+#include "common.h"
+#include "smallmat.h"
+
+namespace eigupd {
+
+constexpr double EPSU = 1.1102230246251565e-16;  // 2^-53
+
+template <int K>
+struct Cfg {
+  static constexpr int NS = K * (K + 1) / 2;
+  static constexpr int WV = (K <= 1) ? 16 : (K <= 3) ? 8 : (K <= 4) ? 4 : 2;
+  static constexpr int RPB = 32;          // roots (or poles) per block
+  static constexpr int SPLIT = 64 / RPB;  // parts of a wave sharing one root
+  static constexpr int TP = 128;          // poles per LDS tile per wave
+};
+
+template <int K, int TP>
+struct PoleTile {
+  double d[TP];
+  double u[TP][K];
+};
+
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
+// Calls f(r, u) for the poles [jb, je) of this wave, with r = 1/(tau - (d_j - d_o))
+// (0 for a pole at distance 0, i.e. x on the pole); part `part` of the wave (of
+// SPLIT) takes poles jb + part, jb + part + SPLIT, ...  Tiles of TP poles go
+// global -> registers (one tile ahead) -> LDS, and every lane of a part reads the
+// same pole.
+template <int K, int TP, int SPLIT, typename F>
+__device__ __forceinline__ void sweep_poles(const double* __restrict__ rd,
+                                            const double* __restrict__ ru, int jb, int je,
+                                            double tau, double d_o, PoleTile<K, TP>& tile, F&& f) {
+  constexpr int PER = TP / 64;
+  const int lane = threadIdx.x & 63;
+  const int part = lane / (64 / SPLIT);
+  double pd[PER], pu[PER][K];
+  auto load = [&](int base) {
+#pragma unroll
+    for (int p = 0; p < PER; ++p) {
+      const int j = base + p * 64 + lane;
+      const bool ok = j < je;
+      pd[p] = ok ? rd[j] : 0.0;
+#pragma unroll
+      for (int c = 0; c < K; ++c) pu[p][c] = ok ? ru[(size_t)j * K + c] : 0.0;
+    }
+  };
+  if (jb < je) load(jb);
+  for (int base = jb; base < je; base += TP) {
+#pragma unroll
+    for (int p = 0; p < PER; ++p) {
+      tile.d[p * 64 + lane] = pd[p];
+#pragma unroll
+      for (int c = 0; c < K; ++c) tile.u[p * 64 + lane][c] = pu[p][c];
+    }
+    wave_sync();
+    if (base + TP < je) load(base + TP);
+    const int cnt = min(TP, je - base);
+#pragma unroll 2
+    for (int q = part; q < cnt; q += SPLIT) {
+      double u[K];
+#pragma unroll
+      for (int c = 0; c < K; ++c) u[c] = tile.u[q][c];
+      f(recip(tau - (tile.d[q] - d_o)), u);
+    }
+    wave_sync();
+  }
+}
+
+// Adds up the partial sums of the SPLIT parts of a wave (every lane gets the total).
+template <int SPLIT, int N>
+__device__ __forceinline__ void combine_parts(double (&a)[N]) {
+#pragma unroll
+  for (int off = 32; off >= 64 / SPLIT; off >>= 1)
+#pragma unroll
+    for (int e = 0; e < N; ++e) a[e] += __shfl_xor(a[e], off, 64);
+}
+
+// S = sum_j u_j u_j^T r_j (without -Sigma) and G = sum_j (u_j r_j)(u_j r_j)^T over this
+// wave's poles, combined across the parts of the wave.
+template <int K, int TP, int SPLIT>
+__device__ __forceinline__ void sweep(const double* __restrict__ rd, const double* __restrict__ ru,
+                                      int jb, int je, double tau, double d_o,
+                                      double (&S)[Sym<K>::NS], double (&G)[Sym<K>::NS],
+                                      PoleTile<K, TP>& tile) {
+  constexpr int NS = Sym<K>::NS;
+#pragma unroll
+  for (int e = 0; e < NS; ++e) {
+    S[e] = 0.0;
+    G[e] = 0.0;
+  }
+  sweep_poles<K, TP, SPLIT>(rd, ru, jb, je, tau, d_o, tile, [&](double r, const double (&u)[K]) {
+    double v[K];
+#pragma unroll
+    for (int c = 0; c < K; ++c) v[c] = u[c] * r;
+#pragma unroll
+    for (int a = 0; a < K; ++a)
+#pragma unroll
+      for (int b = a; b < K; ++b) {
+        S[Sym<K>::at(a, b)] = fma(u[a], v[b], S[Sym<K>::at(a, b)]);
+        G[Sym<K>::at(a, b)] = fma(v[a], v[b], G[Sym<K>::at(a, b)]);
+      }
+  });
+  combine_parts<SPLIT>(S);
+  combine_parts<SPLIT>(G);
+}
+
+// ---------------------------------------------------------------------------
+// Pole counts nu(d_s) for every segment s.
+// ---------------------------------------------------------------------------
+template <int K>
+__global__ __launch_bounds__(64 * Cfg<K>::WV) void polecount_kernel(Work w) {
+  constexpr int NS = Sym<K>::NS, WV = Cfg<K>::WV, RPB = Cfg<K>::RPB, TP = Cfg<K>::TP;
+  __shared__ double s_part[WV][NS][RPB];
+  __shared__ PoleTile<K, TP> s_tile[WV];
+  if (update_cancelled(w.st)) return;
+  const int n_s = w.info->n_s, n_d = w.info->n_d;
+  const int s0 = blockIdx.x * RPB;
+  if (s0 >= n_s) return;
+  const int lane = threadIdx.x & 63, slot = lane % RPB;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int s = min(s0 + slot, n_s - 1);
+  const int st = w.seg_start[s];
+  const double d_s = w.rd[st];
+  const int chunk = (n_d + WV - 1) / WV;
+  const int jb = min(n_d, wv * chunk), je = min(n_d, jb + chunk);
+  double T[NS], G[NS];
+  // tau = 0 at origin d_s: x - d_j = d_s - d_j; rows of segment s give 0 and are skipped
+  sweep<K, TP, Cfg<K>::SPLIT>(w.rd, w.ru, jb, je, 0.0, d_s, T, G, s_tile[wv]);
+  if (lane < RPB) {
+#pragma unroll
+    for (int e = 0; e < NS; ++e) s_part[wv][e][slot] = T[e];
+  }
+  __syncthreads();
+  if (wv != 0 || lane >= RPB || s0 + slot >= n_s) return;
+#pragma unroll
+  for (int e = 0; e < NS; ++e) {
+    double acc = 0.0;
+    for (int q = 0; q < WV; ++q) acc += s_part[q][e][slot];
+    T[e] = acc;
+  }
+#pragma unroll
+  for (int c = 0; c < K; ++c) T[Sym<K>::at(c, c)] -= ((w.sig_pos_mask >> c) & 1) ? 1.0 : -1.0;
+  const int r = max(1, min(w.seg_r[s], K));
+  double Y[K][K];
+#pragma unroll
+  for (int h = 0; h < K; ++h)
+#pragma unroll
+    for (int c = 0; c < K; ++c) Y[h][c] = w.ru[(size_t)(st + min(h, r - 1)) * K + c];
+  const int neg = neg_count_compressed<K>(T, Y, r);
+  w.nu[s] = st + r + neg - w.info->p;
+}
+
+// ---------------------------------------------------------------------------
+// Location: make the pole counts monotone, then give every root its interval.
+// ---------------------------------------------------------------------------
+constexpr int LNT = 1024;
+
+__global__ __launch_bounds__(LNT) void locate_kernel(Work w) {
+  __shared__ int shi[LNT / 64 + 1];
+  __shared__ int s_carry;
+  if (update_cancelled(w.st)) return;
+  const int n_s = w.info->n_s, n_d = w.info->n_d;
+  if (threadIdx.x == 0) s_carry = 0;
+  __syncthreads();
+  // running maximum, clamped to [0, n_d]
+  for (int base = 0; base < n_s; base += LNT) {
+    const int s = base + threadIdx.x;
+    int v = (s < n_s) ? min(max(w.nu[s], 0), n_d) : 0;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+      const int t = __shfl_up(v, off, 64);
+      if (lane >= off) v = max(v, t);
+    }
+    __syncthreads();
+    if (lane == 63) shi[wv] = v;
+    __syncthreads();
+    int pre = s_carry;
+    for (int q = 0; q < wv; ++q) pre = max(pre, shi[q]);
+    v = max(v, pre);
+    if (s < n_s) w.nu[s] = v;
+    __syncthreads();
+    if (threadIdx.x == LNT - 1) s_carry = v;
+    __syncthreads();
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t <= n_s; t += LNT) {
+    const int lo = (t == 0) ? 0 : w.nu[t - 1];
+    const int hi = (t == n_s) ? n_d : w.nu[t];
+    for (int i = lo; i < hi; ++i) {
+      w.root_t[i] = t;
+      w.root_clo[i] = lo;
+      w.root_chi[i] = hi;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Root refinement.
+// ---------------------------------------------------------------------------
+enum { PH_FIRST = 0, PH_SOLVE = 1, PH_DONE = 2 };
+
+// Newton steps below STAG |tau| that no longer halve have reached the rounding
+// floor of the secular sums; the iteration stops there.
+constexpr double STAG = 1e-9;
+
+template <int K>
+__global__ __launch_bounds__(64 * Cfg<K>::WV) void rootsolve_kernel(Work w) {
+  constexpr int NS = Sym<K>::NS, WV = Cfg<K>::WV, RPB = Cfg<K>::RPB, TP = Cfg<K>::TP;
+  __shared__ double s_part[WV][2 * NS][RPB];
+  __shared__ PoleTile<K, TP> s_tile[WV];
+  __shared__ double s_tau[RPB], s_do[RPB];
+  __shared__ int s_any;
+  if (update_cancelled(w.st)) return;
+  const int n_d = w.info->n_d, n_s = w.info->n_s;
+  const int i0 = blockIdx.x * RPB;
+  if (i0 >= n_d) return;
+  const int lane = threadIdx.x & 63, slot = lane % RPB;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int chunk = (n_d + WV - 1) / WV;
+  const int jb = min(n_d, wv * chunk), je = min(n_d, jb + chunk);
+
+  // solver state, meaningful in lanes 0..RPB-1 of wave 0
+  const int i = i0 + slot;
+  const bool owner = (wv == 0) && (lane < RPB);
+  const bool valid = owner && (i < n_d);
+  const int tgt = i + 1;
+  int phase = valid ? PH_FIRST : PH_DONE;
+  int t = 0, clo = 0, chi = 0, evals = 0, rows_below = 0;
+  double a = 0.0, b = 0.0, ra = 0.0, rb = 0.0, tlo = 0.0, thi = 0.0, tau = 0.0;
+  double dxold = 0.0, dprev = INFINITY, d_o = 0.0;
+  int o_seg = 0;
+  bool two_sided = false, last_newton = false;
+  if (valid) {
+    t = min(max(w.root_t[i], 0), n_s);
+    clo = w.root_clo[i];
+    chi = w.root_chi[i];
+    rows_below = w.seg_start[t];  // rows strictly below any x inside interval t
+    const bool has_a = t > 0, has_b = t < n_s;
+    two_sided = has_a && has_b;
+    if (has_a) {
+      a = w.rd[w.seg_start[t - 1]];
+      ra = (double)w.seg_r[t - 1];
+    }
+    if (has_b) {
+      b = w.rd[w.seg_start[t]];
+      rb = (double)w.seg_r[t];
+    }
+    if (two_sided) {
+      o_seg = t - 1;
+      d_o = a;
+      tlo = 0.0;
+      thi = b - a;
+      tau = 0.5 * thi;
+    } else if (has_a) {  // right of the last pole
+      o_seg = t - 1;
+      d_o = a;
+      tlo = 0.0;
+      thi = w.info->upper - a;
+      tau = 0.5 * thi;
+    } else {  // left of the first pole
+      o_seg = t;
+      d_o = b;
+      tlo = w.info->lower - b;
+      thi = 0.0;
+      tau = 0.5 * tlo;
+    }
+    dxold = thi - tlo;
+  }
+  if (owner) {
+    s_tau[slot] = tau;
+    s_do[slot] = d_o;
+  }
+  __syncthreads();
+
+  for (;;) {
+    double S[NS], G[NS];
+    sweep<K, TP, Cfg<K>::SPLIT>(w.rd, w.ru, jb, je, s_tau[slot], s_do[slot], S, G, s_tile[wv]);
+    if (lane < RPB) {
+#pragma unroll
+      for (int e = 0; e < NS; ++e) {
+        s_part[wv][e][slot] = S[e];
+        s_part[wv][NS + e][slot] = G[e];
+      }
+    }
+    __syncthreads();
+    if (wv == 0) {
+      if (phase != PH_DONE) {
+#pragma unroll
+        for (int e = 0; e < NS; ++e) {
+          double as = 0.0, ag = 0.0;
+          for (int q = 0; q < WV; ++q) {
+            as += s_part[q][e][slot];
+            ag += s_part[q][NS + e][slot];
+          }
+          S[e] = as;
+          G[e] = ag;
+        }
+#pragma unroll
+        for (int c = 0; c < K; ++c)
+          S[Sym<K>::at(c, c)] -= ((w.sig_pos_mask >> c) & 1) ? 1.0 : -1.0;
+        // S(x) = V diag(theta) V^T: inertia, and tr(S^{-1} S') = -sum_m v_m^T G v_m / theta_m
+        double V[K][K];
+        jacobi_eig<K, true>(S, V);
+        int neg = 0;
+        double phi = 0.0;
+#pragma unroll
+        for (int m = 0; m < K; ++m) {
+          const double th = S[Sym<K>::at(m, m)];
+          neg += (th < 0.0) ? 1 : 0;
+          double vgv = 0.0;
+#pragma unroll
+          for (int p2 = 0; p2 < K; ++p2) {
+            double gv = 0.0;
+#pragma unroll
+            for (int q2 = 0; q2 < K; ++q2) gv += G[Sym<K>::at(p2, q2)] * V[q2][m];
+            vgv += V[p2][m] * gv;
+          }
+          phi -= vgv / th;
+        }
+        ++evals;
+        const int cnt = rows_below + neg - w.info->p;
+        // d log g / dx = ra/(x-a) + rb/(x-b) + tr(S^{-1} S'); the Newton step is -1/that
+        double da, db;
+        if (o_seg == t - 1) {
+          da = tau;
+          db = tau - (b - a);
+        } else {
+          da = tau + (b - a);
+          db = tau;
+        }
+        if (ra > 0.0) phi += ra / da;
+        if (rb > 0.0) phi += rb / db;
+        const double delta = -1.0 / phi;
+        if (phase == PH_FIRST) {
+          phase = PH_SOLVE;
+          if (two_sided && cnt < tgt) {
+            // the root lies in the right half: move the origin to b
+            o_seg = t;
+            d_o = b;
+            const double gap = b - a;
+            tau -= gap;
+            tlo -= gap;
+            thi = 0.0;
+          }
+        }
+        if (cnt >= tgt) {
+          thi = tau;
+          chi = cnt;
+        } else {
+          tlo = tau;
+          clo = cnt;
+        }
+        const double width = thi - tlo;
+        const double mid = tlo + 0.5 * width;
+        const bool isolated = (clo == tgt - 1) && (chi == tgt);
+        double next = mid;
+        bool conv = false;
+        if (width <= 4.0 * EPSU * fmax(fabs(tlo), fabs(thi))) {
+          conv = true;
+        } else if (isolated && isfinite(delta)) {
+          const double tn = tau + delta;
+          const double ad = fabs(delta);
+          if (ad <= 4.0 * EPSU * fabs(tn) || (ad <= STAG * fabs(tn) && ad > 0.5 * fabs(dprev))) {
+            conv = true;
+            next = fmin(fmax(tn, tlo), thi);
+          } else if (tn > tlo && tn < thi && (!last_newton || ad <= 0.5 * fabs(dxold))) {
+            // an in-bracket Newton step is taken unless the previous step was one
+            // too and this one does not halve it
+            dxold = delta;
+            next = tn;
+          } else {
+            dxold = 0.5 * width;
+          }
+          dprev = delta;
+        }
+        last_newton = !conv && (next != mid);
+        if (!conv && evals >= MAX_EVALS) {
+          conv = true;
+          atomicOr(&w.st->status, ST_NOCONV);
+        }
+        if (!conv && !(next > tlo && next < thi)) next = mid;
+        if (next == 0.0) next = (tlo == 0.0) ? thi : tlo;
+        tau = next;
+        if (conv) {
+          phase = PH_DONE;
+          w.root_o[i] = o_seg;
+          w.root_tau[i] = tau;
+          w.root_clo[i] = clo;
+          w.root_chi[i] = chi;
+          w.root_it[i] = evals;
+        }
+      }
+      if (owner) {
+        s_tau[slot] = tau;
+        s_do[slot] = d_o;
+      }
+      const unsigned long long live = __ballot(phase != PH_DONE);
+      if (lane == 0) s_any = (live != 0ull);
+    }
+    __syncthreads();
+    if (!s_any) break;
+  }
+  if (valid) {
+    atomicMin(&w.info->it_min, evals);
+    atomicMax(&w.info->it_max, evals);
+    atomicAdd((unsigned long long*)&w.info->it_sum, (unsigned long long)evals);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Null vectors at the converged roots (Sec. 2.4).  c is the eigenvector of the
+// smallest-magnitude eigenvalue of S(lambda'), scaled so that the eigenvector
+// w = (lambda' I - D)^{-1} U c has unit norm.  The norm is summed explicitly,
+// ||w||^2 = sum_j (u_j^T c)^2 / (lambda' - d_j)^2 with each dot product formed
+// first: near a pole the quadratic form c^T G c would cancel.  A bracket that
+// still holds m_c > 1 roots (a multiple root the count could not split) is
+// solved once, at the point of its first root: its m_c smallest-magnitude
+// eigenvectors are orthonormalised in the inner product of the w's (their Gram
+// matrix summed the same way), and root number pos of the bracket takes vector
+// pos.
+// ---------------------------------------------------------------------------
+template <int K>
+__global__ __launch_bounds__(64 * Cfg<K>::WV) void rootvec_kernel(Work w) {
+  constexpr int NS = Sym<K>::NS, WV = Cfg<K>::WV, RPB = Cfg<K>::RPB, TP = Cfg<K>::TP;
+  constexpr int SPLIT = Cfg<K>::SPLIT;
+  __shared__ double s_part[WV][2 * NS][RPB];
+  __shared__ PoleTile<K, TP> s_tile[WV];
+  __shared__ double s_C[K][K][RPB];
+  __shared__ double s_tau[RPB], s_do[RPB];
+  __shared__ int s_mc[RPB], s_cluster;
+  if (update_cancelled(w.st)) return;
+  const int n_d = w.info->n_d, n_s = w.info->n_s;
+  const int i0 = blockIdx.x * RPB;
+  if (i0 >= n_d) return;
+  const int lane = threadIdx.x & 63, slot = lane % RPB;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int chunk = (n_d + WV - 1) / WV;
+  const int jb = min(n_d, wv * chunk), je = min(n_d, jb + chunk);
+  const bool owner = (wv == 0) && (lane < RPB);
+  const int i = min(i0 + slot, n_d - 1);
+  const int clo = w.root_clo[i], chi = w.root_chi[i];
+  const int m_c = min(max(chi - clo, 1), K);
+  const int pos = min(max(i - clo, 0), m_c - 1);
+  if (owner) {
+    // a multiple root is solved at the point of its first root
+    int src = i;
+    if (m_c > 1) {
+      const int c0 = min(max(clo, 0), n_d - 1);
+      if (w.root_o[c0] == w.root_o[i]) src = c0;
+    }
+    s_tau[slot] = w.root_tau[src];
+    s_do[slot] = w.rd[w.seg_start[min(max(w.root_o[src], 0), n_s - 1)]];
+    s_mc[slot] = (i0 + slot < n_d) ? m_c : 1;
+    const unsigned long long multi = __ballot(i0 + slot < n_d && m_c > 1);
+    if (lane == 0) s_cluster = (multi != 0ull);
+  }
+  __syncthreads();
+  const double tau = s_tau[slot], d_o = s_do[slot];
+  double S[NS], G[NS];
+  sweep<K, TP, SPLIT>(w.rd, w.ru, jb, je, tau, d_o, S, G, s_tile[wv]);
+  if (lane < RPB) {
+#pragma unroll
+    for (int e = 0; e < NS; ++e) s_part[wv][e][slot] = S[e];
+  }
+  __syncthreads();
+  if (owner) {
+#pragma unroll
+    for (int e = 0; e < NS; ++e) {
+      double as = 0.0;
+      for (int q = 0; q < WV; ++q) as += s_part[q][e][slot];
+      S[e] = as;
+    }
+#pragma unroll
+    for (int c = 0; c < K; ++c) S[Sym<K>::at(c, c)] -= ((w.sig_pos_mask >> c) & 1) ? 1.0 : -1.0;
+    double V[K][K];
+    jacobi_eig<K, true>(S, V);
+    // candidate vectors: eigenvectors ordered by |theta| ascending
+#pragma unroll
+    for (int m = 0; m < K; ++m) {
+      const double am = fabs(S[Sym<K>::at(m, m)]);
+      int rk = 0;
+#pragma unroll
+      for (int m2 = 0; m2 < K; ++m2) {
+        const double a2 = fabs(S[Sym<K>::at(m2, m2)]);
+        rk += (a2 < am || (a2 == am && m2 < m)) ? 1 : 0;
+      }
+#pragma unroll
+      for (int c = 0; c < K; ++c) s_C[rk][c][slot] = V[c][m];
+    }
+  }
+  __syncthreads();
+  // second pass: Gram matrix of the candidates' eigenvectors (just ||w||^2 when
+  // no root of the block is multiple)
+  double gram[NS];
+#pragma unroll
+  for (int e = 0; e < NS; ++e) gram[e] = 0.0;
+  if (!s_cluster) {
+    double c0[K];
+#pragma unroll
+    for (int c = 0; c < K; ++c) c0[c] = s_C[0][c][slot];
+    sweep_poles<K, TP, SPLIT>(w.rd, w.ru, jb, je, tau, d_o, s_tile[wv],
+                              [&](double r, const double (&u)[K]) {
+                                double z = 0.0;
+#pragma unroll
+                                for (int c = 0; c < K; ++c) z = fma(u[c], c0[c], z);
+                                z *= r;
+                                gram[0] = fma(z, z, gram[0]);
+                              });
+  } else {
+    double Cm[K][K];
+#pragma unroll
+    for (int a = 0; a < K; ++a)
+#pragma unroll
+      for (int c = 0; c < K; ++c) Cm[a][c] = s_C[a][c][slot];
+    sweep_poles<K, TP, SPLIT>(w.rd, w.ru, jb, je, tau, d_o, s_tile[wv],
+                              [&](double r, const double (&u)[K]) {
+                                double z[K];
+#pragma unroll
+                                for (int a = 0; a < K; ++a) {
+                                  double t = 0.0;
+#pragma unroll
+                                  for (int c = 0; c < K; ++c) t = fma(u[c], Cm[a][c], t);
+                                  z[a] = t * r;
+                                }
+#pragma unroll
+                                for (int a = 0; a < K; ++a)
+#pragma unroll
+                                  for (int b = a; b < K; ++b)
+                                    gram[Sym<K>::at(a, b)] =
+                                        fma(z[a], z[b], gram[Sym<K>::at(a, b)]);
+                              });
+  }
+  combine_parts<SPLIT>(gram);
+  __syncthreads();
+  if (lane < RPB) {
+#pragma unroll
+    for (int e = 0; e < NS; ++e) s_part[wv][e][slot] = gram[e];
+  }
+  __syncthreads();
+  if (!owner || i0 + slot >= n_d) return;
+#pragma unroll
+  for (int e = 0; e < NS; ++e) {
+    double as = 0.0;
+    for (int q = 0; q < WV; ++q) as += s_part[q][e][slot];
+    gram[e] = as;
+  }
+  double out[K];
+  if (m_c == 1) {
+    const double inv = (gram[0] > 0.0) ? 1.0 / sqrt(gram[0]) : 0.0;
+#pragma unroll
+    for (int c = 0; c < K; ++c) out[c] = s_C[0][c][slot] * inv;
+  } else {
+    // Gram-Schmidt of the candidates in the Gram inner product, on coefficient
+    // vectors x (candidate a has x = e_a); vector pos is kept
+    double X[K][K];
+#pragma unroll
+    for (int r = 0; r < K; ++r)
+#pragma unroll
+      for (int a = 0; a < K; ++a) X[r][a] = (r == a) ? 1.0 : 0.0;
+#pragma unroll
+    for (int r = 0; r < K; ++r) {
+      if (r < m_c) {
+#pragma unroll
+        for (int l = 0; l < K; ++l) {
+          if (l < r) {
+            const double g = quad<K>(gram, X[l], X[r]);
+#pragma unroll
+            for (int a = 0; a < K; ++a) X[r][a] -= g * X[l][a];
+          }
+        }
+        const double nn = sqrt(fmax(quad<K>(gram, X[r], X[r]), 0.0));
+        const double inv = (nn > 0.0) ? 1.0 / nn : 0.0;
+#pragma unroll
+        for (int a = 0; a < K; ++a) X[r][a] *= inv;
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < K; ++c) {
+      double acc = 0.0;
+#pragma unroll
+      for (int r = 0; r < K; ++r)
+#pragma unroll
+        for (int a = 0; a < K; ++a) acc += (r == pos && a < m_c) ? X[r][a] * s_C[a][c][slot] : 0.0;
+      out[c] = acc;
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < K; ++c) w.root_c[(size_t)i * K + c] = out[c];
+  if (m_c > 1) {
+    // every root of the bracket uses the common point
+    w.root_tau[i] = tau;
+  }
+}
+
+template <int K>
+static hipError_t polecount_launch(const Work& w, hipStream_t s) {
+  const int grid = (w.n + Cfg<K>::RPB - 1) / Cfg<K>::RPB;
+  hipLaunchKernelGGL((polecount_kernel<K>), dim3(grid), dim3(64 * Cfg<K>::WV), 0, s, w);
+  return hipGetLastError();
+}
+
+template <int K>
+static hipError_t rootsolve_launch(const Work& w, hipStream_t s) {
+  const int grid = (w.n + Cfg<K>::RPB - 1) / Cfg<K>::RPB;
+  hipLaunchKernelGGL((rootsolve_kernel<K>), dim3(grid), dim3(64 * Cfg<K>::WV), 0, s, w);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((rootvec_kernel<K>), dim3(grid), dim3(64 * Cfg<K>::WV), 0, s, w);
+  return hipGetLastError();
+}
+
+#define EIGUPD_DISPATCH_K(fn)                 \
+  switch (w.k) {                              \
+    case 1: return fn<1>(w, s);               \
+    case 2: return fn<2>(w, s);               \
+    case 3: return fn<3>(w, s);               \
+    case 4: return fn<4>(w, s);               \
+    case 5: return fn<5>(w, s);               \
+    case 6: return fn<6>(w, s);               \
+    case 7: return fn<7>(w, s);               \
+    case 8: return fn<8>(w, s);               \
+    default: return hipErrorInvalidValue;     \
+  }
+
+hipError_t launch_polecount(const Work& w, hipStream_t s) { EIGUPD_DISPATCH_K(polecount_launch) }
+
+hipError_t launch_rootsolve(const Work& w, hipStream_t s) { EIGUPD_DISPATCH_K(rootsolve_launch) }
+
+hipError_t launch_locate(const Work& w, hipStream_t s) {
+  hipLaunchKernelGGL(locate_kernel, dim3(1), dim3(LNT), 0, s, w);
+  return hipGetLastError();
+}
+
+}  // namespace eigupd

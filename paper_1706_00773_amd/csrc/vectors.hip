@@ -1,0 +1,231 @@
+// vectors.hip -- ordering of the new eigenvalues and the eigenvector matrix W
+// in the Q basis (Sec. 2.4, eq. (10)).
+//
+// finalize   one block: absolute root values d_o + tau, made monotone by a
+//            running maximum, merged with the deflated eigenvalues (ascending);
+//            writes lambda' and one ColParam per output column.
+// wbuild     W(j, p) = u_j^T c_p / (tau_p - (d_j - d_o,p)) for kept rows j of a
+//            root column p (c_p is scaled so that the column has unit norm and
+//            signed so that its entry at the first row of its origin pole is
+//            positive); deflated columns are unit vectors.  Bound by the n^2
+//            FP64 stores, which are coalesced (threads span rows).
+// group_reflect  maps rows of W that belong to a merged equal-pole group back
+//            from the rotated basis (Householder reflectors of the deflation).
+// commit     counts the update as committed unless an error was raised.
+#include "common.h"
+
+namespace eigupd {
+
+constexpr int FNT = 1024;
+
+__device__ __forceinline__ int count_less(const double* v, int n, double x) {
+  int lo = 0, hi = n;
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (v[mid] < x)
+      lo = mid + 1;
+    else
+      hi = mid;
+  }
+  return lo;
+}
+
+__device__ __forceinline__ int count_less_equal(const double* v, int n, double x) {
+  int lo = 0, hi = n;
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (v[mid] <= x)
+      lo = mid + 1;
+    else
+      hi = mid;
+  }
+  return lo;
+}
+
+template <int K>
+__global__ __launch_bounds__(FNT) void finalize_kernel(Work w, double* lam_dst) {
+  __shared__ double s_carry;
+  __shared__ double shd[FNT / 64];
+  if (update_cancelled(w.st)) return;
+  const int n_d = w.info->n_d, n_defl = w.info->n_defl;
+  if (threadIdx.x == 0) s_carry = -INFINITY;
+  __syncthreads();
+  // absolute root values, running maximum
+  for (int base = 0; base < n_d; base += FNT) {
+    const int i = base + threadIdx.x;
+    double x = -INFINITY;
+    if (i < n_d) x = w.rd[w.seg_start[w.root_o[i]]] + w.root_tau[i];
+    double v = wave_incl_max(x);
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 63) shd[wv] = v;
+    __syncthreads();
+    double pre = s_carry;
+    for (int q = 0; q < wv; ++q) pre = fmax(pre, shd[q]);
+    v = fmax(v, pre);
+    if (i < n_d) w.xs[i] = v;
+    __syncthreads();
+    if (threadIdx.x == FNT - 1) s_carry = v;
+    __syncthreads();
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < n_d; i += FNT) {
+    const double x = w.xs[i];
+    const int pos = i + count_less(w.dval, n_defl, x);
+    lam_dst[pos] = x;
+    ColParam cp;
+    const int o = w.root_o[i];
+    const int jo = w.seg_start[o];
+    cp.d_o = w.rd[jo];
+    cp.tau = w.root_tau[i];
+    double dot = 0.0;
+#pragma unroll
+    for (int c = 0; c < K; ++c) dot += w.ru[(size_t)jo * K + c] * w.root_c[(size_t)i * K + c];
+    const double sgn = (dot / cp.tau < 0.0) ? -1.0 : 1.0;
+#pragma unroll
+    for (int c = 0; c < KMAX; ++c) cp.c[c] = (c < K) ? sgn * w.root_c[(size_t)i * K + c] : 0.0;
+    cp.drow = -1;
+    cp.pad = 0;
+    w.colp[pos] = cp;
+  }
+  for (int j = threadIdx.x; j < n_defl; j += FNT) {
+    const double v = w.dval[j];
+    const int pos = j + count_less_equal(w.xs, n_d, v);
+    lam_dst[pos] = v;
+    ColParam cp;
+    cp.d_o = 0.0;
+    cp.tau = 0.0;
+#pragma unroll
+    for (int c = 0; c < KMAX; ++c) cp.c[c] = 0.0;
+    cp.drow = w.drow[j];
+    cp.pad = 0;
+    w.colp[pos] = cp;
+  }
+}
+
+// W tile: 256 rows x CB columns per block.
+template <int K, int CB>
+__global__ __launch_bounds__(256) void wbuild_kernel(Work w) {
+  if (update_cancelled(w.st)) return;
+  const int n = w.n;
+  const int r = blockIdx.x * 256 + threadIdx.x;
+  const int p0 = blockIdx.y * CB;
+  const int pe = min(n, p0 + CB);
+  if (r >= n) return;
+  const int jr = w.rmap[r];
+  double dj = 0.0, u[K];
+#pragma unroll
+  for (int c = 0; c < K; ++c) u[c] = 0.0;
+  if (jr >= 0) {
+    dj = w.rd[jr];
+#pragma unroll
+    for (int c = 0; c < K; ++c) u[c] = w.ru[(size_t)jr * K + c];
+  }
+  double* __restrict__ Wc = w.W;
+  for (int p = p0; p < pe; ++p) {
+    const ColParam& cp = w.colp[p];
+    double val;
+    if (cp.drow >= 0) {
+      val = (r == cp.drow) ? 1.0 : 0.0;
+    } else {
+      double num = 0.0;
+#pragma unroll
+      for (int c = 0; c < K; ++c) num = fma(u[c], cp.c[c], num);
+      const double y = cp.tau - (dj - cp.d_o);
+      val = (jr >= 0) ? num / y : 0.0;
+    }
+    Wc[(size_t)p * n + r] = val;
+  }
+}
+
+// One wave per column; every merged group's rows are mapped back with
+// H_0 H_1 ... H_{h-1} (the last reflector first).
+template <int K>
+__global__ __launch_bounds__(256) void group_reflect_kernel(Work w) {
+  if (update_cancelled(w.st)) return;
+  const int n_mg = w.info->n_groups;
+  if (n_mg == 0) return;
+  const int n = w.n;
+  const int lane = threadIdx.x & 63;
+  const int p = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (p >= n) return;
+  double* col = w.W + (size_t)p * n;
+  for (int gi = 0; gi < n_mg; ++gi) {
+    const int g = w.mg_list[gi];
+    const int first = w.g_first[g], m = w.g_m[g], h = w.g_h[g];
+    for (int hh = h - 1; hh >= 0; --hh) {
+      double d = 0.0;
+      for (int t = hh + lane; t < m; t += 64)
+        d += w.hv[(size_t)(first + t) * K + hh] * col[w.nt_list[first + t]];
+      d = wave_sum(d) * w.hbeta[(size_t)g * K + hh];
+      for (int t = hh + lane; t < m; t += 64)
+        col[w.nt_list[first + t]] -= d * w.hv[(size_t)(first + t) * K + hh];
+    }
+  }
+}
+
+__global__ void commit_kernel(Work w) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    if (w.st->status == 0) w.st->gen += 1;
+  }
+}
+
+template <int K>
+static hipError_t finalize_launch(const Work& w, double* lam_dst, hipStream_t s) {
+  hipLaunchKernelGGL((finalize_kernel<K>), dim3(1), dim3(FNT), 0, s, w, lam_dst);
+  return hipGetLastError();
+}
+
+hipError_t launch_finalize(const Work& w, double* lam_dst, hipStream_t s) {
+  switch (w.k) {
+    case 1: return finalize_launch<1>(w, lam_dst, s);
+    case 2: return finalize_launch<2>(w, lam_dst, s);
+    case 3: return finalize_launch<3>(w, lam_dst, s);
+    case 4: return finalize_launch<4>(w, lam_dst, s);
+    case 5: return finalize_launch<5>(w, lam_dst, s);
+    case 6: return finalize_launch<6>(w, lam_dst, s);
+    case 7: return finalize_launch<7>(w, lam_dst, s);
+    case 8: return finalize_launch<8>(w, lam_dst, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <int K>
+static hipError_t wbuild_launch(const Work& w, hipStream_t s) {
+  constexpr int CB = 32;
+  dim3 grid((w.n + 255) / 256, (w.n + CB - 1) / CB);
+  hipLaunchKernelGGL((wbuild_kernel<K, CB>), grid, dim3(256), 0, s, w);
+  return hipGetLastError();
+}
+
+template <int K>
+static hipError_t group_reflect_launch(const Work& w, hipStream_t s) {
+  hipLaunchKernelGGL((group_reflect_kernel<K>), dim3((w.n + 3) / 4), dim3(256), 0, s, w);
+  return hipGetLastError();
+}
+
+#define EIGUPD_DISPATCH_K2(fn)                \
+  switch (w.k) {                              \
+    case 1: return fn<1>(w, s);               \
+    case 2: return fn<2>(w, s);               \
+    case 3: return fn<3>(w, s);               \
+    case 4: return fn<4>(w, s);               \
+    case 5: return fn<5>(w, s);               \
+    case 6: return fn<6>(w, s);               \
+    case 7: return fn<7>(w, s);               \
+    case 8: return fn<8>(w, s);               \
+    default: return hipErrorInvalidValue;     \
+  }
+
+hipError_t launch_wbuild(const Work& w, hipStream_t s) { EIGUPD_DISPATCH_K2(wbuild_launch) }
+
+hipError_t launch_group_reflect(const Work& w, hipStream_t s) {
+  EIGUPD_DISPATCH_K2(group_reflect_launch)
+}
+
+hipError_t launch_commit(const Work& w, hipStream_t s) {
+  hipLaunchKernelGGL(commit_kernel, dim3(1), dim3(64), 0, s, w);
+  return hipGetLastError();
+}
+
+}  // namespace eigupd

@@ -331,3 +331,26 @@ def test_golden_regression():
     assert np.abs(lo - np.array(g["lam_new"])).max() <= 1e-15
     Qg = np.array(g["Q_new"]).reshape(12, 12, order="F")
     assert np.abs(Qo - Qg).max() <= 1e-14
+
+
+def test_roots_within_rounding_of_a_pole():
+    """Rows of U of norm 1e-14 put a root within 1e-28 of their pole; the eigenvector
+    (about e_j in the Q basis) must still match LAPACK's."""
+    n, k = 60, 2
+    u = wl.random_small(n, k, seed=61)
+    Qn = np.asarray(u.Q)
+    U = Qn.T @ u.K
+    rows = [3, 17, 40]
+    U[rows] *= (1e-14 / np.linalg.norm(U[rows], axis=1))[:, None]
+    K = np.asfortranarray(Qn @ U)
+    A = wl.explicit_matrix(u.lam, Qn, K, u.sigma)
+    ev, V = np.linalg.eigh(A)
+    lo, Qo, _ = oracle.update(u.lam, Qn, K, u.sigma)
+    scale = np.abs(ev).max()
+    assert np.abs(lo - ev).max() <= 1e-13 * scale
+    assert np.abs(Qo.T @ Qo - np.eye(n)).max() <= 1e-12
+    d = np.diff(ev)
+    gaps = np.minimum(np.r_[d, np.inf], np.r_[np.inf, d])
+    for i in np.nonzero(gaps > 1e-6)[0]:
+        s = np.sign(Qo[:, i] @ V[:, i])
+        assert np.abs(Qo[:, i] - s * V[:, i]).max() <= 1e-9
