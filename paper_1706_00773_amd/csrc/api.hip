@@ -98,6 +98,7 @@ size_t carve(eig_state_s* s, void* base) {
   w.root_chi = c.take<int>(n);
   w.root_o = c.take<int>(n);
   w.root_tau = c.take<double>(n);
+  w.root_tv = c.take<double>(n);
   w.root_c = c.take<double>(n * KMAX);
   w.root_it = c.take<int>(n);
   w.xs = c.take<double>(n);

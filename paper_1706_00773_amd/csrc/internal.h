@@ -94,6 +94,7 @@ struct Work {
   int* root_chi;    // n   count at the interval's right end
   int* root_o;      // n   origin segment
   double* root_tau; // n
+  double* root_tv;  // n   offset at which the root's null vector was formed
   double* root_c;   // n*KMAX
   int* root_it;     // n
   double* xs;       // n   absolute root values (monotone)

@@ -451,13 +451,19 @@ __global__ __launch_bounds__(64 * Cfg<K>::WV) void rootsolve_kernel(Work w) {
 // smallest-magnitude eigenvalue of S(lambda'), scaled so that the eigenvector
 // w = (lambda' I - D)^{-1} U c has unit norm.  The norm is summed explicitly,
 // ||w||^2 = sum_j (u_j^T c)^2 / (lambda' - d_j)^2 with each dot product formed
-// first: near a pole the quadratic form c^T G c would cancel.  A bracket that
-// still holds m_c > 1 roots (a multiple root the count could not split) is
-// solved once, at the point of its first root: its m_c smallest-magnitude
-// eigenvectors are orthonormalised in the inner product of the w's (their Gram
-// matrix summed the same way), and root number pos of the bracket takes vector
-// pos.
+// first (near a pole the quadratic form c^T G c would cancel).
+//
+// A cluster -- consecutive roots of one pole interval whose offsets agree to
+// CLUSTER_TOL -- is a multiple (or numerically multiple) eigenvalue: its null
+// vectors are not determined one by one.  All its roots are solved at the point
+// of its first root: the m smallest-magnitude eigenvectors of S are made
+// orthonormal in the inner product of the w's (Gram matrix summed the same
+// way), and a Rayleigh-Ritz step separates them: for G-orthonormal C,
+// W^T (D + U Sigma U^T) W = x I + C^T (S Sigma S + S) C, a k-by-k quantity.
+// Root number pos of the cluster takes the Ritz vector of rank pos.
 // ---------------------------------------------------------------------------
+constexpr double CLUSTER_TOL = 1e-8;
+
 template <int K>
 __global__ __launch_bounds__(64 * Cfg<K>::WV) void rootvec_kernel(Work w) {
   constexpr int NS = Sym<K>::NS, WV = Cfg<K>::WV, RPB = Cfg<K>::RPB, TP = Cfg<K>::TP;
@@ -465,8 +471,9 @@ __global__ __launch_bounds__(64 * Cfg<K>::WV) void rootvec_kernel(Work w) {
   __shared__ double s_part[WV][2 * NS][RPB];
   __shared__ PoleTile<K, TP> s_tile[WV];
   __shared__ double s_C[K][K][RPB];
+  __shared__ double s_th[K][RPB];
   __shared__ double s_tau[RPB], s_do[RPB];
-  __shared__ int s_mc[RPB], s_cluster;
+  __shared__ int s_mc[RPB], s_pos[RPB], s_cluster;
   if (update_cancelled(w.st)) return;
   const int n_d = w.info->n_d, n_s = w.info->n_s;
   const int i0 = blockIdx.x * RPB;
@@ -477,20 +484,29 @@ __global__ __launch_bounds__(64 * Cfg<K>::WV) void rootvec_kernel(Work w) {
   const int jb = min(n_d, wv * chunk), je = min(n_d, jb + chunk);
   const bool owner = (wv == 0) && (lane < RPB);
   const int i = min(i0 + slot, n_d - 1);
-  const int clo = w.root_clo[i], chi = w.root_chi[i];
-  const int m_c = min(max(chi - clo, 1), K);
-  const int pos = min(max(i - clo, 0), m_c - 1);
   if (owner) {
-    // a multiple root is solved at the point of its first root
-    int src = i;
-    if (m_c > 1) {
-      const int c0 = min(max(clo, 0), n_d - 1);
-      if (w.root_o[c0] == w.root_o[i]) src = c0;
+    // the cluster [cs, ce) around root i
+    const int oi = w.root_o[i], ti = w.root_t[i];
+    auto close = [&](int a, int b) {
+      const double ta = w.root_tau[a], tb = w.root_tau[b];
+      return w.root_o[a] == oi && w.root_o[b] == oi && w.root_t[a] == ti && w.root_t[b] == ti &&
+             fabs(ta - tb) <= CLUSTER_TOL * fmax(fabs(ta), fabs(tb));
+    };
+    int cs = i, ce = i + 1;
+    for (int j = i - 1; j >= max(0, i - (K - 1)); --j) {
+      if (!close(j, j + 1)) break;
+      cs = j;
     }
-    s_tau[slot] = w.root_tau[src];
-    s_do[slot] = w.rd[w.seg_start[min(max(w.root_o[src], 0), n_s - 1)]];
-    s_mc[slot] = (i0 + slot < n_d) ? m_c : 1;
-    const unsigned long long multi = __ballot(i0 + slot < n_d && m_c > 1);
+    for (int j = i + 1; j < min(n_d, cs + K); ++j) {
+      if (!close(j - 1, j)) break;
+      ce = j + 1;
+    }
+    const int m_c = (i0 + slot < n_d) ? ce - cs : 1;
+    s_mc[slot] = m_c;
+    s_pos[slot] = i - cs;
+    s_tau[slot] = w.root_tau[cs];
+    s_do[slot] = w.rd[w.seg_start[min(max(oi, 0), n_s - 1)]];
+    const unsigned long long multi = __ballot(m_c > 1);
     if (lane == 0) s_cluster = (multi != 0ull);
   }
   __syncthreads();
@@ -513,7 +529,7 @@ __global__ __launch_bounds__(64 * Cfg<K>::WV) void rootvec_kernel(Work w) {
     for (int c = 0; c < K; ++c) S[Sym<K>::at(c, c)] -= ((w.sig_pos_mask >> c) & 1) ? 1.0 : -1.0;
     double V[K][K];
     jacobi_eig<K, true>(S, V);
-    // candidate vectors: eigenvectors ordered by |theta| ascending
+    // candidates: eigenvectors of S ordered by |theta| ascending
 #pragma unroll
     for (int m = 0; m < K; ++m) {
       const double am = fabs(S[Sym<K>::at(m, m)]);
@@ -525,11 +541,12 @@ __global__ __launch_bounds__(64 * Cfg<K>::WV) void rootvec_kernel(Work w) {
       }
 #pragma unroll
       for (int c = 0; c < K; ++c) s_C[rk][c][slot] = V[c][m];
+      s_th[rk][slot] = S[Sym<K>::at(m, m)];
     }
   }
   __syncthreads();
   // second pass: Gram matrix of the candidates' eigenvectors (just ||w||^2 when
-  // no root of the block is multiple)
+  // the block holds no cluster)
   double gram[NS];
 #pragma unroll
   for (int e = 0; e < NS; ++e) gram[e] = 0.0;
@@ -583,19 +600,21 @@ __global__ __launch_bounds__(64 * Cfg<K>::WV) void rootvec_kernel(Work w) {
     for (int q = 0; q < WV; ++q) as += s_part[q][e][slot];
     gram[e] = as;
   }
+  const int m_c = min(s_mc[slot], K);
+  const int pos = min(max(s_pos[slot], 0), m_c - 1);
   double out[K];
   if (m_c == 1) {
     const double inv = (gram[0] > 0.0) ? 1.0 / sqrt(gram[0]) : 0.0;
 #pragma unroll
     for (int c = 0; c < K; ++c) out[c] = s_C[0][c][slot] * inv;
   } else {
-    // Gram-Schmidt of the candidates in the Gram inner product, on coefficient
-    // vectors x (candidate a has x = e_a); vector pos is kept
+    // Gram-Schmidt of the m_c candidates in the Gram inner product, on
+    // coefficient vectors (candidate a is e_a); rows r >= m_c stay unused
     double X[K][K];
 #pragma unroll
     for (int r = 0; r < K; ++r)
 #pragma unroll
-      for (int a = 0; a < K; ++a) X[r][a] = (r == a) ? 1.0 : 0.0;
+      for (int a = 0; a < K; ++a) X[r][a] = (r == a && r < m_c) ? 1.0 : 0.0;
 #pragma unroll
     for (int r = 0; r < K; ++r) {
       if (r < m_c) {
@@ -613,22 +632,67 @@ __global__ __launch_bounds__(64 * Cfg<K>::WV) void rootvec_kernel(Work w) {
         for (int a = 0; a < K; ++a) X[r][a] *= inv;
       }
     }
+    // Rayleigh-Ritz: in candidate coordinates S acts as diag(theta), so
+    // C^T (S Sigma S + S) C = Theta (Cc^T Sigma Cc) Theta + Theta
+    double th[K];
+#pragma unroll
+    for (int a = 0; a < K; ++a) th[a] = s_th[a][slot];
+    double Hc[Sym<K>::NS];
+#pragma unroll
+    for (int a = 0; a < K; ++a)
+#pragma unroll
+      for (int b = a; b < K; ++b) {
+        double m = 0.0;
+#pragma unroll
+        for (int c = 0; c < K; ++c)
+          m += s_C[a][c][slot] * (((w.sig_pos_mask >> c) & 1) ? 1.0 : -1.0) * s_C[b][c][slot];
+        Hc[Sym<K>::at(a, b)] = th[a] * m * th[b] + ((a == b) ? th[a] : 0.0);
+      }
+    double H[Sym<K>::NS];
+    double hscale = 0.0;
+#pragma unroll
+    for (int a = 0; a < K; ++a) hscale = fmax(hscale, fabs(th[a]));
+#pragma unroll
+    for (int r = 0; r < K; ++r)
+#pragma unroll
+      for (int q = r; q < K; ++q) {
+        double acc = quad<K>(Hc, X[r], X[q]);
+        if (r >= m_c || q >= m_c) acc = (r == q) ? 4.0 * hscale + 1.0 : 0.0;
+        H[Sym<K>::at(r, q)] = acc;
+      }
+    double Y[K][K];
+    jacobi_eig<K, true>(H, Y);
+    // the Ritz vector of rank pos (ascending Ritz value)
+    double z[K];
+#pragma unroll
+    for (int a = 0; a < K; ++a) z[a] = 0.0;
+#pragma unroll
+    for (int m = 0; m < K; ++m) {
+      const double hm = H[Sym<K>::at(m, m)];
+      int rk = 0;
+#pragma unroll
+      for (int m2 = 0; m2 < K; ++m2) {
+        const double h2 = H[Sym<K>::at(m2, m2)];
+        rk += (h2 < hm || (h2 == hm && m2 < m)) ? 1 : 0;
+      }
+      if (rk == pos) {
+#pragma unroll
+        for (int r = 0; r < K; ++r)
+#pragma unroll
+          for (int a = 0; a < K; ++a) z[a] += Y[r][m] * X[r][a];
+      }
+    }
 #pragma unroll
     for (int c = 0; c < K; ++c) {
       double acc = 0.0;
 #pragma unroll
-      for (int r = 0; r < K; ++r)
-#pragma unroll
-        for (int a = 0; a < K; ++a) acc += (r == pos && a < m_c) ? X[r][a] * s_C[a][c][slot] : 0.0;
+      for (int a = 0; a < K; ++a) acc += z[a] * s_C[a][c][slot];
       out[c] = acc;
     }
   }
 #pragma unroll
   for (int c = 0; c < K; ++c) w.root_c[(size_t)i * K + c] = out[c];
-  if (m_c > 1) {
-    // every root of the bracket uses the common point
-    w.root_tau[i] = tau;
-  }
+  w.root_tv[i] = tau;
 }
 
 template <int K>

@@ -77,7 +77,7 @@ __global__ __launch_bounds__(FNT) void finalize_kernel(Work w, double* lam_dst) 
     const int o = w.root_o[i];
     const int jo = w.seg_start[o];
     cp.d_o = w.rd[jo];
-    cp.tau = w.root_tau[i];
+    cp.tau = w.root_tv[i];
     double dot = 0.0;
 #pragma unroll
     for (int c = 0; c < K; ++c) dot += w.ru[(size_t)jo * K + c] * w.root_c[(size_t)i * K + c];

@@ -262,3 +262,36 @@ def test_host_input_path():
         s.query(lo, Qo)
     ref_lam, ref_Q, _ = oracle.update(u.lam, u.Q, u.K, u.sigma)
     _check_full(u, lo, Qo, ref_lam, ref_Q)
+
+
+def test_double_root_away_from_poles():
+    """Two decoupled rank-1 blocks sharing a root: an exact double eigenvalue inside
+    one pole interval; the cluster branch must return orthonormal eigenvectors."""
+    import math
+
+    lam = np.array([0.0, 0.5, 1.0, 2.0])
+    za = np.array([0.9, 0.3])
+    f = lambda x: 1 + za[0] ** 2 / (0 - x) + za[1] ** 2 / (1 - x)
+    lo_, hi_ = 1e-9, 1 - 1e-9
+    for _ in range(200):
+        mid = (lo_ + hi_) / 2
+        if f(mid) < 0:
+            lo_ = mid
+        else:
+            hi_ = mid
+    r = (lo_ + hi_) / 2
+    zb1 = 0.6
+    zb3sq = -(1 + zb1 ** 2 / (0.5 - r)) * (2.0 - r)
+    K = np.zeros((4, 2), order="F")
+    K[0, 0], K[2, 0] = za
+    K[1, 1], K[3, 1] = zb1, math.sqrt(zb3sq)
+    sig = np.array([1, 1], dtype=np.int8)
+    rng = np.random.default_rng(4)
+    Q = wl.orthogonal_from(rng.standard_normal((4, 4)))
+    Kq = np.asfortranarray(np.asarray(Q) @ K)
+    lo, Qo, info, _ = run_update(lam, Q, Kq, sig)
+    A = wl.explicit_matrix(lam, Q, Kq, sig)
+    ev = np.linalg.eigvalsh(A)
+    assert np.abs(lo - ev).max() <= 1e-14
+    assert np.abs(Qo.T @ Qo - np.eye(4)).max() <= 1e-10
+    assert np.abs(A @ Qo - Qo * lo).max() <= 1e-10
