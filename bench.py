@@ -117,6 +117,11 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-roots", type=int, default=2048)
     ap.add_argument("--cpu-cols", type=int, default=1024)
+    ap.add_argument("--save-input", metavar="NPZ",
+                    help="only generate the resident decomposition and write it to NPZ")
+    ap.add_argument("--load-input", metavar="NPZ",
+                    help="read the resident decomposition from NPZ (written by --save-input) "
+                         "instead of generating it")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (for HBM counter calibration)")
     args = ap.parse_args()
@@ -143,13 +148,25 @@ def main():
         return
     n, k = args.n, args.k
     log = lambda *a: print(*a, file=sys.stderr, flush=True)
-    log(f"[bench] generating n={n} k={k} inputs on {dev}")
-    if k == 2:
-        u = wl.plain_rank2(n, seed=1000, device=str(dev), min_gap=1e-12)
+    if args.load_input:
+        log(f"[bench] reading the n={n} decomposition from {args.load_input}")
+        with np.load(args.load_input) as z:
+            lam0 = z["lam"].copy()
+            Q0 = torch.from_numpy(z["Qt"]).to(dev).t()  # stored transposed: column-major
+        if lam0.size != n:
+            raise SystemExit(f"{args.load_input} holds n={lam0.size}, not {n}")
     else:
-        u = wl.general_rankk(k, n=n, device=str(dev))
-    lam0 = u.lam.copy()
-    Q0 = u.Q  # torch, column-major
+        log(f"[bench] generating n={n} k={k} inputs on {dev}")
+        if k == 2:
+            u = wl.plain_rank2(n, seed=1000, device=str(dev), min_gap=1e-12)
+        else:
+            u = wl.general_rankk(k, n=n, device=str(dev))
+        lam0 = u.lam.copy()
+        Q0 = u.Q  # torch, column-major
+    if args.save_input:
+        np.savez(args.save_input, lam=lam0, Qt=Q0.t().contiguous().cpu().numpy())
+        log(f"[bench] wrote {args.save_input}")
+        return
     steps, warm = args.steps, args.warmup
     perts = make_perturbations(n, k, warm + 2 * steps, seed=2000, dev=dev)
     state = eu.EigState(n, 0)

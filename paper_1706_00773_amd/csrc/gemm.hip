@@ -12,14 +12,16 @@
 // consume the current one, one barrier per slice.  Block ids are remapped so
 // that the blocks resident on one XCD (blocks are dealt round-robin to the 8
 // XCDs) cover one compact group of 8 tile rows, sharing its A panel and the B
-// panels in that XCD's L2.
+// panels in that XCD's L2.  LDS rows are padded to 144 doubles (288 dwords, an
+// odd multiple of 32 banks), so the four k-rows an MFMA fragment read touches
+// fall in alternating bank halves and the fragment reads are conflict free.
 #include "common.h"
 
 namespace eigupd {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
 
-constexpr int GBM = 128, GBN = 128, GBK = 16, GPAD = 4, GNT = 256;
+constexpr int GBM = 128, GBN = 128, GBK = 16, GPAD = 16, GNT = 256;
 constexpr int GGROUP = 8;
 
 __device__ __forceinline__ void tile_of(int bid, int tiles_m, int tiles_n, int* tm, int* tn) {
@@ -51,7 +53,9 @@ __global__ __launch_bounds__(GNT, 2) void dgemm_kernel(int M, int N, int Kd,
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int wm = (wv & 1) * 64, wn = (wv >> 1) * 64;
   // global load assignment
-  const int a_k = tid >> 4, a_m = (tid & 15) * 8;  // A: column k0+a_k, rows m0+a_m .. +8
+  // A: column k0+a_k, rows m0+a_m+32q .. +2 (q = 0..3): each group of 16 lanes
+  // writes one full 128-double LDS row, so the 16-byte stores do not collide
+  const int a_k = tid >> 4, a_m = (tid & 15) * 2;
   const int b_n = tid >> 1, b_k = (tid & 1) * 8;   // B: column n0+b_n, rows k0+b_k .. +8
   const bool full_m = vec && (m0 + GBM <= M), full_n = vec && (n0 + GBN <= N);
   double ra[8], rb[8];
@@ -60,17 +64,16 @@ __global__ __launch_bounds__(GNT, 2) void dgemm_kernel(int M, int N, int Kd,
     const bool full_k = (k0 + GBK <= Kd);
     const int ka = k0 + a_k;
     if (full_m && full_k) {
-      const double2* src = reinterpret_cast<const double2*>(A + (size_t)ka * lda + m0 + a_m);
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        const double2 v = src[q];
+        const double2 v = *reinterpret_cast<const double2*>(A + (size_t)ka * lda + m0 + a_m + 32 * q);
         ra[2 * q] = v.x;
         ra[2 * q + 1] = v.y;
       }
     } else {
 #pragma unroll
       for (int q = 0; q < 8; ++q) {
-        const int r = m0 + a_m + q;
+        const int r = m0 + a_m + 32 * (q >> 1) + (q & 1);
         ra[q] = (r < M && ka < Kd) ? A[(size_t)ka * lda + r] : 0.0;
       }
     }
@@ -93,7 +96,8 @@ __global__ __launch_bounds__(GNT, 2) void dgemm_kernel(int M, int N, int Kd,
   };
   auto sstore = [&](int buf) {
 #pragma unroll
-    for (int q = 0; q < 8; ++q) As[buf][a_k][a_m + q] = ra[q];
+    for (int q = 0; q < 4; ++q)
+      *reinterpret_cast<double2*>(&As[buf][a_k][a_m + 32 * q]) = double2{ra[2 * q], ra[2 * q + 1]};
 #pragma unroll
     for (int q = 0; q < 8; ++q) Bs[buf][b_k + q][b_n] = rb[q];
   };
