@@ -16,7 +16,8 @@
  *     safeguarded Newton/bisection (the zero finder of Sec. 2.3)
  *   eigenvectors w = (lambda' I - diag(lambda))^{-1} U c, normalised
  *     (Sec. 2.4, eq. (10)), back-transformed Q' = Q W.
- * Everything runs in FP64 on the device.
+ * Everything runs in FP64 on the device unless a reduced-precision mode is
+ * asked for (see the mode bits).
  *
  * Conventions common to all entry points
  *   - Matrices are column-major.  lambda is ascending.
@@ -79,9 +80,32 @@ enum {
   EIG_ENONFINITE = -9    /* NaN or Inf in an input or in U */
 };
 
-/* Mode bits of eig_update_rankk. */
+/* Mode bits of eig_update_rankk.  Bits 0-1 select the arithmetic of the two
+ * dense products U = Q^T K and Q' = Q W; the secular roots, the pole
+ * differences and the deflation tests are FP64 in every mode.
+ *   EIG_GEMM_FP64         both products in FP64 (FP64 matrix cores for Q W).
+ *   EIG_GEMM_FP32_CORR    operands split x = hi + lo into two FP32 numbers;
+ *                         Q W = hi*hi + (hi*lo + lo*hi) on FP32 matrix cores
+ *                         with FP32 accumulation, the partial sums of every
+ *                         16-deep k-slice added up in FP64.
+ *   EIG_GEMM_BF16X3_CORR  operands split into three bfloat16 numbers; the six
+ *                         products b_i*b_j with i + j <= 2 on BF16 matrix
+ *                         cores with FP32 accumulation, every 32-deep k-slice
+ *                         added up in FP64.
+ * In both reduced modes U is formed the same way (on the vector units) and
+ * then corrected once in FP64: U = U0 + lo(Q^T (K - Q U0)) with K - Q U0
+ * formed in FP64, which brings U back to FP64 accuracy.  The eigenvectors
+ * carry the rounding of the reduced Q W (about 1e-7 relative); the
+ * eigenvalues do not.  Q and W are split once per update into slice planes:
+ * the first update of a state in a reduced mode (without EIG_VALUES_ONLY)
+ * allocates them, 12 n^2 bytes for BF16X3 and 16 n^2 bytes for FP32, and the
+ * state keeps them until eig_state_destroy (a later update that needs more
+ * synchronises the device and reallocates). */
 enum {
-  EIG_GEMM_FP64 = 0,        /* Q^T K and Q W in FP64 */
+  EIG_GEMM_FP64 = 0,
+  EIG_GEMM_FP32_CORR = 1,
+  EIG_GEMM_BF16X3_CORR = 2,
+  EIG_GEMM_MASK = 3,
   EIG_VALUES_ONLY = 1 << 4, /* eigenvalues only: nothing is committed, eig_query
                                returns these values until the next update */
   EIG_HOST_INPUT = 1 << 6,  /* K is a host pointer (copied before return) */
@@ -94,7 +118,8 @@ enum { EIG_KMAX = 8 };
 /* Create a state for matrices of order n on HIP device `device`, and allocate
  * all its device memory: two copies of (lambda, Q) used alternately, the
  * n-by-n eigenvector matrix W and O(n * EIG_KMAX) of workspace -- about
- * 24 n^2 bytes.  No later call allocates device memory.
+ * 24 n^2 bytes.  Only the first reduced-precision update allocates more
+ * (the slice planes described at the mode bits); no other call does.
  * Errors: EIG_EINVAL (out NULL, n < 1), EIG_EDEVICE, EIG_ENOMEM.
  * On success *out owns the memory until eig_state_destroy. */
 int eig_state_create(eig_state_t *out, int64_t n, int32_t device);
@@ -113,12 +138,14 @@ int eig_state_upload(eig_state_t s, const double *lambda, const double *Q, int64
  *   K      n-by-k column-major, leading dimension ldk >= n; a device pointer
  *          unless mode has EIG_HOST_INPUT
  *   sigma  host array of k entries, each +1 or -1
- *   mode   EIG_GEMM_FP64, optionally | EIG_VALUES_ONLY | EIG_HOST_INPUT
- *          | EIG_PHASE_TIMING
+ *   mode   one of EIG_GEMM_FP64, EIG_GEMM_FP32_CORR, EIG_GEMM_BF16X3_CORR,
+ *          optionally | EIG_VALUES_ONLY | EIG_HOST_INPUT | EIG_PHASE_TIMING
  * Asynchronous: enqueues the kernels on `hip_stream` and returns.  On the
  * device the update writes the new pair into the state's other buffer and
  * commits it only if no error was raised; the state then holds A'.
- * Errors (synchronous): EIG_EINVAL, EIG_EUNSUPPORTED (k > EIG_KMAX),
+ * Errors (synchronous): EIG_EINVAL, EIG_EUNSUPPORTED (k > EIG_KMAX, an
+ * unknown mode bit, or precision selector 3), EIG_ENOMEM (slice planes of a
+ * reduced mode could not be allocated),
  * EIG_ESTATE (no upload yet), EIG_EDEVICE (launch failure).  Deferred:
  * EIG_ENONFINITE, EIG_ENOCONV (see the file header). */
 int eig_update_rankk(eig_state_t s, int64_t k, const double *K, int64_t ldk,

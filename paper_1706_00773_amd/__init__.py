@@ -33,6 +33,9 @@ EIG_ESTATE = -8
 EIG_ENONFINITE = -9
 
 EIG_GEMM_FP64 = 0
+EIG_GEMM_FP32_CORR = 1
+EIG_GEMM_BF16X3_CORR = 2
+EIG_GEMM_MASK = 3
 EIG_VALUES_ONLY = 1 << 4
 EIG_HOST_INPUT = 1 << 6
 EIG_PHASE_TIMING = 1 << 7

@@ -22,6 +22,8 @@ struct eig_state_s {
   double* Q[2] = {nullptr, nullptr};
   double* lam_vo = nullptr;
   double* Kbuf = nullptr;
+  void* lp_block = nullptr;  // slice planes of the reduced-precision modes (lazily)
+  size_t lp_bytes = 0;
   Work w{};
   hipEvent_t ev[9] = {};
   bool timed = false;
@@ -103,6 +105,8 @@ size_t carve(eig_state_s* s, void* base) {
   w.root_it = c.take<int>(n);
   w.xs = c.take<double>(n);
   w.colp = c.take<ColParam>(n);
+  w.lp_part = c.take<double>((size_t)LP_RESID_CHUNKS * n * KMAX);
+  w.lp_resid = c.take<double>(n * KMAX);
   w.st = c.take<DevState>(1);
   w.info = c.take<DevInfo>(1);
   return c.off + 256;
@@ -189,6 +193,7 @@ int eig_state_destroy(eig_state_t s) {
     for (auto& e : s->ev)
       if (e) (void)hipEventDestroy(e);
     if (s->block) (void)hipFree(s->block);
+    if (s->lp_block) (void)hipFree(s->lp_block);
   }
   delete s;
   return EIG_OK;
@@ -230,8 +235,11 @@ int eig_update_rankk(eig_state_t s, int64_t k, const double* K, int64_t ldk, con
   if (!s || !K || !sigma || k < 1 || ldk < s->n) return EIG_EINVAL;
   if (k > EIG_KMAX) return EIG_EUNSUPPORTED;
   if (k > s->n) return EIG_EINVAL;
-  const uint32_t known = EIG_VALUES_ONLY | EIG_HOST_INPUT | EIG_PHASE_TIMING;
+  const uint32_t known = EIG_GEMM_MASK | EIG_VALUES_ONLY | EIG_HOST_INPUT | EIG_PHASE_TIMING;
   if (mode & ~known) return EIG_EUNSUPPORTED;
+  const int prec = (int)(mode & EIG_GEMM_MASK);
+  if (prec != EIG_GEMM_FP64 && prec != EIG_GEMM_FP32_CORR && prec != EIG_GEMM_BF16X3_CORR)
+    return EIG_EUNSUPPORTED;
   int mask = 0;
   for (int64_t c = 0; c < k; ++c) {
     if (sigma[c] == 1)
@@ -267,8 +275,30 @@ int eig_update_rankk(eig_state_t s, int64_t k, const double* K, int64_t ldk, con
     return timed ? hipEventRecord(s->ev[i], st) : hipSuccess;
   };
   const bool vo = (mode & EIG_VALUES_ONLY) != 0;
+  if (prec != EIG_GEMM_FP64 && !vo) {
+    // slice planes of Q and W for the matrix-core product, kept for later updates
+    const size_t need = 2 * lp_plane_bytes(prec, (int)n);
+    if (s->lp_bytes < need) {
+      if (s->lp_block) {
+        HIPCHK(hipStreamSynchronize(st));
+        HIPCHK(hipDeviceSynchronize());
+        (void)hipFree(s->lp_block);
+        s->lp_block = nullptr;
+        s->lp_bytes = 0;
+      }
+      if (hipMalloc(&s->lp_block, need) != hipSuccess) {
+        (void)hipGetLastError();
+        s->lp_block = nullptr;
+        return EIG_ENOMEM;
+      }
+      s->lp_bytes = need;
+    }
+  }
   HIPCHK(mark(0));
-  HIPCHK(launch_qtk(w, st));
+  if (prec == EIG_GEMM_FP64)
+    HIPCHK(launch_qtk(w, st));
+  else
+    HIPCHK(launch_qtk_lp(w, prec, st));
   HIPCHK(mark(1));
   HIPCHK(launch_deflate(w, st));
   HIPCHK(mark(2));
@@ -292,8 +322,12 @@ int eig_update_rankk(eig_state_t s, int64_t k, const double* K, int64_t ldk, con
   HIPCHK(launch_wbuild(w, st));
   HIPCHK(launch_group_reflect(w, st));
   HIPCHK(mark(5));
-  HIPCHK(launch_dgemm((int)n, (int)n, (int)n, w.Q_in, (int)n, w.W, (int)n, w.Q_out, (int)n,
-                      &w.st->status, st));
+  if (prec == EIG_GEMM_FP64)
+    HIPCHK(launch_dgemm((int)n, (int)n, (int)n, w.Q_in, (int)n, w.W, (int)n, w.Q_out, (int)n,
+                        &w.st->status, st));
+  else
+    HIPCHK(launch_gemm_lp(w, prec, s->lp_block,
+                          static_cast<char*>(s->lp_block) + s->lp_bytes / 2, st));
   HIPCHK(mark(6));
   HIPCHK(launch_commit(w, st));
   HIPCHK(mark(7));

@@ -17,6 +17,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "eigupd.h"
+
 namespace eigupd {
 
 constexpr int KMAX = 8;
@@ -34,6 +36,9 @@ constexpr double TAU_GAP = 8.0 * 1.1102230246251565e-16;
 
 // Iteration cap per root (count and Newton evaluations together).
 constexpr int MAX_EVALS = 160;
+
+// Column chunks of the FP64 residual K - Q U0 in the reduced-precision modes.
+constexpr int LP_RESID_CHUNKS = 16;
 
 struct DevState {   // persistent for the life of a state
   int32_t status;   // sticky error bits
@@ -100,6 +105,9 @@ struct Work {
   double* xs;       // n   absolute root values (monotone)
   ColParam* colp;   // n
   double* W;        // n*n
+  // reduced-precision modes
+  double* lp_part;  // LP_RESID_CHUNKS*n*KMAX partial products of Q U0
+  double* lp_resid; // n*KMAX residual K - Q U0 (column-major, leading dimension n)
   DevState* st;
   DevInfo* info;
 };
@@ -117,5 +125,12 @@ hipError_t launch_commit(const Work& w, hipStream_t s);
 // C = A * B, column-major, FP64 MFMA.  Skipped on the device when *status != 0.
 hipError_t launch_dgemm(int M, int N, int Kd, const double* A, int lda, const double* B, int ldb,
                         double* C, int ldc, const int32_t* status, hipStream_t s);
+// Reduced-precision variants (prec = EIG_GEMM_FP32_CORR or EIG_GEMM_BF16X3_CORR):
+// U = Q^T K with the FP64 residual correction, and C = A * B on the matrix cores.
+hipError_t launch_qtk_lp(const Work& w, int prec, hipStream_t s);
+// Q_out = Q_in W: splits W and Q into the slice planes qplanes / wplanes (each
+// lp_plane_bytes(prec, n) bytes), then runs the matrix-core product.
+size_t lp_plane_bytes(int prec, int n);
+hipError_t launch_gemm_lp(const Work& w, int prec, void* qplanes, void* wplanes, hipStream_t s);
 
 }  // namespace eigupd

@@ -15,13 +15,13 @@ def colmajor(a, dev):
     return torch.from_numpy(np.ascontiguousarray(a.T)).to(dev).t()
 
 
-def run_update(lam, Q, K, sigma, dev="cuda:0", values_only=False, fetch=()):
+def run_update(lam, Q, K, sigma, dev="cuda:0", values_only=False, fetch=(), prec=0):
     """Upload (lam, Q), apply K diag(sigma) K^T, return (lam', Q', info, extras)."""
     import torch
 
     n = lam.shape[0]
     Qt = Q if isinstance(Q, torch.Tensor) else colmajor(Q, dev)
-    mode = eu.EIG_VALUES_ONLY if values_only else 0
+    mode = (eu.EIG_VALUES_ONLY if values_only else 0) | prec
     extras = {}
     with eu.EigState(n, 0) as s:
         s.upload(torch.as_tensor(np.asarray(lam), device=dev), Qt)
