@@ -183,6 +183,89 @@ def precision_report(args, dev):
             "modes": out}
 
 
+def batch_report(args, dev):
+    """Batched updates of uneven instances: B resident decompositions, n log-uniform
+    in [lo, hi], k from {1, 2, 4, 8}; the same chained updates applied (a) one at a
+    time with eig_update_rankk, (b) as batches without graphs, (c) as batches with the
+    tuned knobs and graph replay.  Every update of every instance is timed, warmups
+    excluded (the first batches of a shape tune and capture)."""
+    import torch
+
+    import paper_1706_00773_amd as eu
+    from paper_1706_00773_amd import workloads as wl
+
+    log = lambda *a: print(*a, file=sys.stderr, flush=True)
+    B = args.batch
+    rng = np.random.default_rng(1006)
+    sizes = wl.serving_sizes(B, args.batch_lo, args.batch_hi, seed=1006)
+    ks = [int(v) for v in rng.choice([1, 2, 4, 8], B)]
+    log(f"[bench] batch report: {B} instances, n in [{min(sizes)}, {max(sizes)}]")
+    decomps = []
+    for i, n in enumerate(sizes):
+        lam = np.sort(rng.uniform(-1.0, 1.0, n))
+        Q = wl.orthogonal_from(wl.gaussian_square(n, rng), str(dev))
+        decomps.append((torch.from_numpy(lam).to(dev), Q))
+    steps, warm = args.steps, 4
+    perts = []
+    for s in range(warm + steps):
+        row = []
+        for n, k in zip(sizes, ks):
+            K = rng.standard_normal((n, k)) / math.sqrt(n)
+            row.append((torch.from_numpy(np.ascontiguousarray(K.T)).to(dev).t(),
+                        wl.random_signs(k, rng)))
+        perts.append(row)
+    states = [eu.EigState(n, 0) for n in sizes]
+
+    def reset():
+        for st, (lam, Q) in zip(states, decomps):
+            st.upload(lam, Q)
+        torch.cuda.synchronize()
+
+    def timed(fn):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        stream = torch.cuda.current_stream()
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for s in range(warm, warm + steps):
+            fn(s)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / steps
+
+    out = {}
+    # (a) one update at a time
+    reset()
+    for s in range(warm):
+        for st, (K, sig) in zip(states, perts[s]):
+            st.update(K, sig)
+    ms = timed(lambda s: [st.update(K, sig) for st, (K, sig) in zip(states, perts[s])])
+    out["single"] = {"ms_per_round": round(ms, 3), "updates_per_s": round(1000.0 * B / ms, 2)}
+    for name, graphs in (("batched_no_graph", 0), ("batched_graph", 1)):
+        reset()
+        with eu.EigBatch(B, 0) as bt:
+            bt.set(eu.EIG_KNOB_GRAPHS, graphs)
+            for s in range(warm):
+                bt.update([(st, K, sig) for st, (K, sig) in zip(states, perts[s])])
+            ms = timed(lambda s: bt.update([(st, K, sig)
+                                            for st, (K, sig) in zip(states, perts[s])]))
+            out[name] = {"ms_per_round": round(ms, 3), "updates_per_s": round(1000.0 * B / ms, 2),
+                         "rootsolve": ("persistent" if bt.get(eu.EIG_KNOB_ROOTSOLVE) ==
+                                       eu.EIG_ROOTSOLVE_PERSISTENT else "grouped"),
+                         "gemm_tile": bt.get(eu.EIG_KNOB_GEMM_TILE),
+                         "graph_launches": bt.get(eu.EIG_STAT_GRAPH_LAUNCHES)}
+    flops = sum(2.0 * n ** 3 for n in sizes)
+    for v in out.values():
+        v["gemm_equiv_tflops"] = round(flops / (v["ms_per_round"] * 1e-3) / 1e12, 2)
+    for st in states:
+        st.close()
+    return {"workload": f"batch of {B} uneven updates per round, n log-uniform in "
+                        f"[{args.batch_lo}, {args.batch_hi}], k from {{1,2,4,8}}, chained",
+            "n": sizes, "k": ks, "rounds_timed": steps, "rounds_warmup": warm,
+            "modes": out,
+            "speedup_graph_vs_single": round(out["single"]["ms_per_round"] /
+                                             out["batched_graph"]["ms_per_round"], 3)}
+
+
 def measured_traffic():
     """HBM bytes per launch of the GEMM from the rocprofv3 FETCH_SIZE / WRITE_SIZE runs
     recorded under profiles/, or None once gemm.hip differs from the measured source."""
@@ -216,6 +299,10 @@ def main():
                          "instead of generating it")
     ap.add_argument("--precision", action="store_true",
                     help="report the reduced-precision modes (use with --n 16384 --k 4)")
+    ap.add_argument("--batch", type=int, default=0,
+                    help="report batched updates of this many uneven instances")
+    ap.add_argument("--batch-lo", type=int, default=256)
+    ap.add_argument("--batch-hi", type=int, default=2048)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (for HBM counter calibration)")
     args = ap.parse_args()
@@ -242,6 +329,9 @@ def main():
         return
     if args.precision:
         print(json.dumps(precision_report(args, dev)), flush=True)
+        return
+    if args.batch:
+        print(json.dumps(batch_report(args, dev)), flush=True)
         return
     n, k = args.n, args.k
     log = lambda *a: print(*a, file=sys.stderr, flush=True)

@@ -169,6 +169,69 @@ int eig_state_destroy(eig_state_t s);
 /* Static, human-readable text for a status code. */
 const char *eig_status_str(int status);
 
+/* ------------------------------------------------------------------ batches
+ * Many updates at once: one update of each of several states (their n and k
+ * may all differ), applied with every phase launched once per distinct k (or
+ * once in all, for Q' = Q W) over descriptor arrays, the root solve possibly
+ * as a persistent kernel drawing (state, block of 32 roots) items from a
+ * queue, and the whole sequence replayed as a HIP graph for every batch of an
+ * already-seen shape.  Each state's result is bitwise the same as with
+ * eig_update_rankk.  This is a throughput form of Sec. 2.1-2.4 for serving
+ * many decompositions; the paper treats one matrix at a time. */
+typedef struct eig_batch_s *eig_batch_t;
+
+typedef struct {
+  eig_state_t state;      /* each state at most once per batch */
+  int64_t k;              /* 1 <= k <= min(n, EIG_KMAX) */
+  const double *K;        /* device pointer, n-by-k column-major */
+  int64_t ldk;            /* >= n */
+  int8_t sigma[EIG_KMAX]; /* first k entries used, each +1 or -1 */
+} eig_batch_item;
+
+/* Create a batch context for up to max_items updates per call on `device`.
+ * It owns a small device area for the per-call descriptors, two pinned host
+ * staging buffers, a private capture stream and the graph cache.
+ * Errors: EIG_EINVAL, EIG_EDEVICE, EIG_ENOMEM. */
+int eig_batch_create(eig_batch_t *out, int32_t max_items, int32_t device);
+
+/* Enqueue one update per item on hip_stream (asynchronous, like
+ * eig_update_rankk; K borrowed until the stream reaches the batch).  mode:
+ * EIG_GEMM_FP64, optionally | EIG_VALUES_ONLY (then nothing is committed and
+ * eig_query returns the values, as for a single update).  A shape -- the
+ * ordered (k, n) list and the mode -- is tuned on its first two calls (those
+ * two synchronise the stream) and captured into a HIP graph on its next call;
+ * later calls with that shape replay the graph.  Calls on one batch context
+ * must be serialised on one stream.  Device errors are per state (sticky in
+ * that state, reported by its eig_query); the other states commit.
+ * Errors (synchronous, nothing enqueued): EIG_EINVAL (bad item, a state twice,
+ * count out of range, a state on another device), EIG_ESTATE (a state not
+ * uploaded), EIG_EUNSUPPORTED (k > EIG_KMAX or other mode bits), EIG_EDEVICE. */
+int eig_update_batch(eig_batch_t b, const eig_batch_item *items, int32_t count, uint32_t mode,
+                     void *hip_stream);
+
+/* Knobs (eig_batch_set) and read-outs (eig_batch_get) of a batch context.
+ *   EIG_KNOB_ROOTSOLVE   EIG_AUTO (tuned), EIG_ROOTSOLVE_GROUPED (one block per
+ *                        item), EIG_ROOTSOLVE_PERSISTENT (queue); get: the form
+ *                        the last call used
+ *   EIG_KNOB_GEMM_TILE   EIG_AUTO, 64 or 128; get: the tile the last call used
+ *   EIG_KNOB_GRAPHS      1 (default) capture and replay graphs, 0 never; get:
+ *                        1 if the last call replayed a graph
+ *   EIG_STAT_GRAPH_LAUNCHES, EIG_STAT_GRAPHS_CACHED (get only)
+ * Errors: EIG_EINVAL. */
+enum {
+  EIG_KNOB_ROOTSOLVE = 1,
+  EIG_KNOB_GEMM_TILE = 2,
+  EIG_KNOB_GRAPHS = 3,
+  EIG_STAT_GRAPH_LAUNCHES = 4,
+  EIG_STAT_GRAPHS_CACHED = 5
+};
+enum { EIG_AUTO = 0, EIG_ROOTSOLVE_GROUPED = 1, EIG_ROOTSOLVE_PERSISTENT = 2 };
+int eig_batch_set(eig_batch_t b, int32_t knob, int32_t value);
+int eig_batch_get(eig_batch_t b, int32_t knob, int64_t *value);
+
+/* Release the context (after synchronising the device). */
+int eig_batch_destroy(eig_batch_t b);
+
 /* Diagnostics: copy an intermediate of the last update to host memory `dst`
  * (`bytes` available) after synchronising `hip_stream`.  `what`:
  *   EIG_DBG_U            U = Q^T K, n-by-k row-major doubles

@@ -51,8 +51,18 @@ EIG_DBG_ROOT_TAU = 7
 EIG_DBG_ROOT_ITERS = 8
 EIG_DBG_W = 9
 
+EIG_KNOB_ROOTSOLVE = 1
+EIG_KNOB_GEMM_TILE = 2
+EIG_KNOB_GRAPHS = 3
+EIG_STAT_GRAPH_LAUNCHES = 4
+EIG_STAT_GRAPHS_CACHED = 5
+EIG_AUTO = 0
+EIG_ROOTSOLVE_GROUPED = 1
+EIG_ROOTSOLVE_PERSISTENT = 2
+
 EXPORTED = ("eig_state_create", "eig_state_upload", "eig_update_rankk", "eig_query",
-            "eig_state_destroy", "eig_status_str", "eig_debug_fetch")
+            "eig_state_destroy", "eig_status_str", "eig_debug_fetch", "eig_batch_create",
+            "eig_update_batch", "eig_batch_set", "eig_batch_get", "eig_batch_destroy")
 
 
 class eig_info(ctypes.Structure):
@@ -76,6 +86,16 @@ class eig_info(ctypes.Structure):
     def as_dict(self):
         return {f: (list(getattr(self, f)) if f == "ms" else getattr(self, f))
                 for f, _ in self._fields_}
+
+
+class eig_batch_item(ctypes.Structure):
+    _fields_ = [
+        ("state", ctypes.c_void_p),
+        ("k", ctypes.c_int64),
+        ("K", ctypes.c_void_p),
+        ("ldk", ctypes.c_int64),
+        ("sigma", ctypes.c_int8 * 8),
+    ]
 
 
 class EigError(RuntimeError):
@@ -107,6 +127,11 @@ def load_library(path: str = LIB_PATH):
     lib.eig_status_str.argtypes = [ctypes.c_int]
     lib.eig_status_str.restype = ctypes.c_char_p
     lib.eig_debug_fetch.argtypes = [vp, i32, vp, i64, vp]
+    lib.eig_batch_create.argtypes = [ctypes.POINTER(vp), i32, i32]
+    lib.eig_update_batch.argtypes = [vp, ctypes.POINTER(eig_batch_item), i32, ctypes.c_uint32, vp]
+    lib.eig_batch_set.argtypes = [vp, i32, i32]
+    lib.eig_batch_get.argtypes = [vp, i32, ctypes.POINTER(i64)]
+    lib.eig_batch_destroy.argtypes = [vp]
     for name in EXPORTED:
         getattr(lib, name).restype = (ctypes.c_char_p if name == "eig_status_str"
                                       else ctypes.c_int)
@@ -237,6 +262,86 @@ def eig_debug_fetch(s, what: int, count: int, dtype, stream=None) -> np.ndarray:
     _check(load_library().eig_debug_fetch(s, int(what), out.ctypes.data, out.nbytes, st),
            "eig_debug_fetch")
     return out
+
+
+def eig_batch_create(max_items: int, device: int = 0):
+    h = ctypes.c_void_p()
+    _check(load_library().eig_batch_create(ctypes.byref(h), int(max_items), int(device)),
+           "eig_batch_create")
+    return h
+
+
+def eig_batch_destroy(b) -> None:
+    _check(load_library().eig_batch_destroy(b), "eig_batch_destroy")
+
+
+def eig_update_batch(b, updates, mode: int = EIG_GEMM_FP64, stream=None) -> None:
+    """updates: sequence of (state handle, K, sigma) with K an n-by-k column-major
+    float64 torch tensor on the state's GPU."""
+    items = (eig_batch_item * len(updates))()
+    keep = []
+    for i, (h, K, sigma) in enumerate(updates):
+        if not _is_torch(K):
+            raise TypeError("batched updates take device tensors for K")
+        n = K.shape[0]
+        k = 1 if K.dim() == 1 else K.shape[1]
+        kp, ldk, _, kk = _colmajor_ptr(K, n)
+        keep.append(kk)
+        items[i].state = h.value if isinstance(h, ctypes.c_void_p) else h
+        items[i].k = k
+        items[i].K = kp
+        items[i].ldk = ldk
+        sig = np.asarray(sigma).ravel()
+        for c in range(min(k, 8)):
+            items[i].sigma[c] = int(sig[c])
+    st = _current_stream(stream)
+    _check(load_library().eig_update_batch(b, items, len(updates), int(mode), st),
+           "eig_update_batch")
+
+
+def eig_batch_set(b, knob: int, value: int) -> None:
+    _check(load_library().eig_batch_set(b, int(knob), int(value)), "eig_batch_set")
+
+
+def eig_batch_get(b, knob: int) -> int:
+    v = ctypes.c_int64()
+    _check(load_library().eig_batch_get(b, int(knob), ctypes.byref(v)), "eig_batch_get")
+    return int(v.value)
+
+
+class EigBatch:
+    """A batch context: one update of each of several states per call."""
+
+    def __init__(self, max_items: int, device: int = 0):
+        self.handle = eig_batch_create(max_items, device)
+
+    def update(self, updates, mode: int = EIG_GEMM_FP64, stream=None):
+        """updates: sequence of (EigState, K, sigma)."""
+        eig_update_batch(self.handle, [(s.handle, K, sig) for s, K, sig in updates], mode,
+                         stream)
+
+    def set(self, knob: int, value: int):
+        eig_batch_set(self.handle, knob, value)
+
+    def get(self, knob: int) -> int:
+        return eig_batch_get(self.handle, knob)
+
+    def close(self):
+        if self.handle is not None:
+            eig_batch_destroy(self.handle)
+            self.handle = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class EigState:

@@ -10,28 +10,10 @@
 
 #include "eigupd.h"
 #include "internal.h"
+#include "state.h"
 
 using namespace eigupd;
 
-struct eig_state_s {
-  int device = 0;
-  int64_t n = 0;
-  void* block = nullptr;
-  size_t block_bytes = 0;
-  double* lam[2] = {nullptr, nullptr};
-  double* Q[2] = {nullptr, nullptr};
-  double* lam_vo = nullptr;
-  double* Kbuf = nullptr;
-  void* lp_block = nullptr;  // slice planes of the reduced-precision modes (lazily)
-  size_t lp_bytes = 0;
-  Work w{};
-  hipEvent_t ev[9] = {};
-  bool timed = false;
-  int64_t enq_gen = 0;
-  bool uploaded = false;
-  bool last_vo = false;
-  int last_k = 0;
-};
 
 namespace {
 
@@ -310,7 +292,8 @@ int eig_update_rankk(eig_state_t s, int64_t k, const double* K, int64_t ldk, con
   s->last_k = (int)k;
   s->timed = timed;
   if (vo) {
-    HIPCHK(launch_finalize(w, s->lam_vo, st));
+    w.lam_fin = s->lam_vo;
+    HIPCHK(launch_finalize(w, st));
     HIPCHK(mark(5));
     HIPCHK(mark(6));
     HIPCHK(mark(7));
@@ -318,7 +301,8 @@ int eig_update_rankk(eig_state_t s, int64_t k, const double* K, int64_t ldk, con
     s->last_vo = true;
     return EIG_OK;
   }
-  HIPCHK(launch_finalize(w, w.lam_out, st));
+  w.lam_fin = w.lam_out;
+  HIPCHK(launch_finalize(w, st));
   HIPCHK(launch_wbuild(w, st));
   HIPCHK(launch_group_reflect(w, st));
   HIPCHK(mark(5));

@@ -7,6 +7,9 @@
 
 namespace eigupd {
 
+// p[0 .. count) = 0 (a kernel, so that it can sit inside a captured graph)
+__global__ void zero_ints_kernel(int* p, int count);
+
 __device__ __forceinline__ bool update_cancelled(const DevState* st) {
   return __builtin_nontemporal_load(&st->status) != 0;
 }

@@ -77,7 +77,7 @@ __device__ void group_qr(const Work& w, int g, double tol_abs, double* rem2) {
 }
 
 template <int K>
-__global__ __launch_bounds__(DNT) void deflate_kernel(Work w) {
+__device__ __forceinline__ void deflate_body(const Work& w) {
   __shared__ double shd[DNT / 64 + 1];
   __shared__ int shi[DNT / 64 + 1];
   __shared__ int s_bad;
@@ -281,6 +281,28 @@ __global__ __launch_bounds__(DNT) void deflate_kernel(Work w) {
     info->it_max = 0;
     info->it_sum = 0;
   }
+}
+
+template <int K>
+__global__ __launch_bounds__(DNT) void deflate_kernel(Work w) {
+  deflate_body<K>(w);
+}
+
+// one block per instance
+template <int K>
+__global__ __launch_bounds__(DNT) void deflate_group(const Work* __restrict__ works) {
+  deflate_body<K>(works[blockIdx.x]);
+}
+
+template <int K>
+static hipError_t deflate_group_launch(const Work* works, int ninst, hipStream_t s) {
+  hipLaunchKernelGGL((deflate_group<K>), dim3(ninst), dim3(DNT), 0, s, works);
+  return hipGetLastError();
+}
+
+hipError_t launch_deflate_group(int k, const Work* works, int ninst, hipStream_t s) {
+  if (ninst <= 0) return hipSuccess;
+  EIGUPD_SWITCH_K(k, deflate_group_launch, works, ninst, s)
 }
 
 template <int K>

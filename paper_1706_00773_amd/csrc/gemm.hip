@@ -38,41 +38,46 @@ __device__ __forceinline__ void tile_of(int bid, int tiles_m, int tiles_n, int* 
   *tn = in / gsz;
 }
 
-__global__ __launch_bounds__(GNT, 2) void dgemm_kernel(int M, int N, int Kd,
-                                                       const double* __restrict__ A, int lda,
-                                                       const double* __restrict__ B, int ldb,
-                                                       double* __restrict__ C, int ldc,
-                                                       const int32_t* status, int tiles_m,
-                                                       int tiles_n, int vec) {
-  if (__builtin_nontemporal_load(status) != 0) return;
-  __shared__ double As[2][GBK][GBM + GPAD];
-  __shared__ double Bs[2][GBK][GBN + GPAD];
-  int tm, tn;
-  tile_of(blockIdx.x, tiles_m, tiles_n, &tm, &tn);
-  const int m0 = tm * GBM, n0 = tn * GBN;
+// One BT x BT tile (tm, tn) of C = A B.  Four waves in a 2 x 2 arrangement, each
+// a (BT/2) x (BT/2) sub-tile of 16 x 16 MFMA tiles.  A thread stages BT/16
+// doubles of the A slice (pairs of rows 32 apart in one k-column) and BT/16 of
+// the B slice (consecutive k of one column of B).  Every tile size runs the
+// same k-slices in the same order, so C is bitwise the same for any BT.
+template <int BT>
+__device__ __forceinline__ void dgemm_tile(int M, int N, int Kd, const double* __restrict__ A,
+                                           int lda, const double* __restrict__ B, int ldb,
+                                           double* __restrict__ C, int ldc, int tm, int tn,
+                                           int vec) {
+  constexpr int WT = BT / 2;          // wave sub-tile
+  constexpr int FT = WT / 16;         // MFMA tiles per wave side
+  constexpr int AQ = BT / 32;         // A row pairs per thread
+  constexpr int TPC = GNT / BT;       // threads per B column
+  constexpr int KPT = GBK / TPC;      // k values per thread of a B column
+  __shared__ double As[2][GBK][BT + GPAD];
+  __shared__ double Bs[2][GBK][BT + GPAD];
+  const int m0 = tm * BT, n0 = tn * BT;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  const int wm = (wv & 1) * 64, wn = (wv >> 1) * 64;
-  // global load assignment
-  // A: column k0+a_k, rows m0+a_m+32q .. +2 (q = 0..3): each group of 16 lanes
-  // writes one full 128-double LDS row, so the 16-byte stores do not collide
+  const int wm = (wv & 1) * WT, wn = (wv >> 1) * WT;
+  // A: column k0+a_k, rows m0+a_m+32q .. +2: each group of 16 lanes writes one
+  // LDS row in 16-byte pairs, so the stores do not collide
   const int a_k = tid >> 4, a_m = (tid & 15) * 2;
-  const int b_n = tid >> 1, b_k = (tid & 1) * 8;   // B: column n0+b_n, rows k0+b_k .. +8
-  const bool full_m = vec && (m0 + GBM <= M), full_n = vec && (n0 + GBN <= N);
-  double ra[8], rb[8];
+  const int b_n = tid / TPC, b_k = (tid % TPC) * KPT;  // B: column n0+b_n, rows k0+b_k ..
+  const bool full_m = vec && (m0 + BT <= M), full_n = vec && (n0 + BT <= N);
+  double ra[2 * AQ], rb[KPT];
 
   auto gload = [&](int k0) {
     const bool full_k = (k0 + GBK <= Kd);
     const int ka = k0 + a_k;
     if (full_m && full_k) {
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
+      for (int q = 0; q < AQ; ++q) {
         const double2 v = *reinterpret_cast<const double2*>(A + (size_t)ka * lda + m0 + a_m + 32 * q);
         ra[2 * q] = v.x;
         ra[2 * q + 1] = v.y;
       }
     } else {
 #pragma unroll
-      for (int q = 0; q < 8; ++q) {
+      for (int q = 0; q < 2 * AQ; ++q) {
         const int r = m0 + a_m + 32 * (q >> 1) + (q & 1);
         ra[q] = (r < M && ka < Kd) ? A[(size_t)ka * lda + r] : 0.0;
       }
@@ -81,14 +86,14 @@ __global__ __launch_bounds__(GNT, 2) void dgemm_kernel(int M, int N, int Kd,
     if (full_n && full_k) {
       const double2* src = reinterpret_cast<const double2*>(B + (size_t)nb * ldb + k0 + b_k);
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
+      for (int q = 0; q < KPT / 2; ++q) {
         const double2 v = src[q];
         rb[2 * q] = v.x;
         rb[2 * q + 1] = v.y;
       }
     } else {
 #pragma unroll
-      for (int q = 0; q < 8; ++q) {
+      for (int q = 0; q < KPT; ++q) {
         const int kk = k0 + b_k + q;
         rb[q] = (nb < N && kk < Kd) ? B[(size_t)nb * ldb + kk] : 0.0;
       }
@@ -96,17 +101,17 @@ __global__ __launch_bounds__(GNT, 2) void dgemm_kernel(int M, int N, int Kd,
   };
   auto sstore = [&](int buf) {
 #pragma unroll
-    for (int q = 0; q < 4; ++q)
+    for (int q = 0; q < AQ; ++q)
       *reinterpret_cast<double2*>(&As[buf][a_k][a_m + 32 * q]) = double2{ra[2 * q], ra[2 * q + 1]};
 #pragma unroll
-    for (int q = 0; q < 8; ++q) Bs[buf][b_k + q][b_n] = rb[q];
+    for (int q = 0; q < KPT; ++q) Bs[buf][b_k + q][b_n] = rb[q];
   };
 
-  d4 acc[4][4];
+  d4 acc[FT][FT];
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < FT; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+    for (int j = 0; j < FT; ++j) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
 
   const int nk = (Kd + GBK - 1) / GBK;
   gload(0);
@@ -119,15 +124,15 @@ __global__ __launch_bounds__(GNT, 2) void dgemm_kernel(int M, int N, int Kd,
 #pragma unroll
     for (int ks = 0; ks < GBK / 4; ++ks) {
       const int kr = ks * 4 + fk;
-      double a[4], b[4];
+      double a[FT], b[FT];
 #pragma unroll
-      for (int i = 0; i < 4; ++i) a[i] = As[cur][kr][wm + i * 16 + fr];
+      for (int i = 0; i < FT; ++i) a[i] = As[cur][kr][wm + i * 16 + fr];
 #pragma unroll
-      for (int j = 0; j < 4; ++j) b[j] = Bs[cur][kr][wn + j * 16 + fr];
+      for (int j = 0; j < FT; ++j) b[j] = Bs[cur][kr][wn + j * 16 + fr];
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
+      for (int i = 0; i < FT; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j)
+        for (int j = 0; j < FT; ++j)
           acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
     }
     if (kt + 1 < nk) sstore(cur ^ 1);
@@ -136,9 +141,9 @@ __global__ __launch_bounds__(GNT, 2) void dgemm_kernel(int M, int N, int Kd,
   // epilogue: lane holds rows l/16 + 4v of column l%16 of each 16x16 tile; for a
   // fixed v the wave writes 4 consecutive rows of 16 columns
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < FT; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
+    for (int j = 0; j < FT; ++j) {
       const int col = n0 + wn + j * 16 + fr;
       if (col < N) {
         double* dst = C + (size_t)col * ldc;
@@ -149,6 +154,60 @@ __global__ __launch_bounds__(GNT, 2) void dgemm_kernel(int M, int N, int Kd,
         }
       }
     }
+}
+
+__global__ __launch_bounds__(GNT, 2) void dgemm_kernel(int M, int N, int Kd,
+                                                       const double* __restrict__ A, int lda,
+                                                       const double* __restrict__ B, int ldb,
+                                                       double* __restrict__ C, int ldc,
+                                                       const int32_t* status, int tiles_m,
+                                                       int tiles_n, int vec) {
+  if (__builtin_nontemporal_load(status) != 0) return;
+  int tm, tn;
+  tile_of(blockIdx.x, tiles_m, tiles_n, &tm, &tn);
+  dgemm_tile<GBM>(M, N, Kd, A, lda, B, ldb, C, ldc, tm, tn, vec);
+}
+
+// Grouped Q' = Q W over several instances: block b is tile b - prefix[i] of
+// instance i (tiles in groups of GGROUP tile rows, column by column).
+template <int BT>
+__global__ __launch_bounds__(GNT, 2) void dgemm_group(const GemmDesc* __restrict__ d,
+                                                      const int* __restrict__ prefix, int ninst) {
+  int lo = 0, hi = ninst - 1;
+  const int b = blockIdx.x;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (prefix[mid] <= b)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  const GemmDesc& g = d[lo];
+  if (__builtin_nontemporal_load(g.status) != 0) return;
+  const int t = b - prefix[lo];
+  const int tiles = (g.n + BT - 1) / BT;
+  const int tpg = GGROUP * tiles;
+  const int first_m = (t / tpg) * GGROUP;
+  const int gsz = min(tiles - first_m, GGROUP);
+  const int in = t % tpg;
+  dgemm_tile<BT>(g.n, g.n, g.n, g.A, g.n, g.B, g.n, g.C, g.n, first_m + in % gsz, in / gsz, g.vec);
+}
+
+int gemm_tiles(int n, int bt) {
+  const int t = (n + bt - 1) / bt;
+  return t * t;
+}
+
+hipError_t launch_dgemm_group(int bt, const GemmDesc* d, const int* prefix, int ninst, int blocks,
+                              hipStream_t s) {
+  if (blocks <= 0) return hipSuccess;
+  if (bt == 128)
+    hipLaunchKernelGGL((dgemm_group<128>), dim3(blocks), dim3(GNT), 0, s, d, prefix, ninst);
+  else if (bt == 64)
+    hipLaunchKernelGGL((dgemm_group<64>), dim3(blocks), dim3(GNT), 0, s, d, prefix, ninst);
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
 }
 
 hipError_t launch_dgemm(int M, int N, int Kd, const double* A, int lda, const double* B, int ldb,

@@ -68,6 +68,7 @@ struct Work {
   const double* Q_in;
   double* lam_out;
   double* Q_out;
+  double* lam_fin;  // where the merged eigenvalues go: lam_out, or a values-only buffer
   const double* K;
   double* U;
   // deflation
@@ -112,19 +113,89 @@ struct Work {
   DevInfo* info;
 };
 
+// A grouped launch runs one kernel over several instances of the same rank k:
+// block b of the grid belongs to the instance i with prefix[i] <= b <
+// prefix[i + 1] and is that instance's block b - prefix[i].
+struct Group {
+  const Work* works;  // ninst descriptors in device memory
+  const int* prefix;  // ninst + 1 block offsets in device memory
+  int ninst;
+};
+
+__device__ __forceinline__ int group_instance(const Group& g, int b) {
+  int lo = 0, hi = g.ninst - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (g.prefix[mid] <= b)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  return lo;
+}
+
+// switch over the compile-time rank: EIGUPD_SWITCH_K(k, fn, args...) returns
+// fn<k>(args...) for k = 1..KMAX
+#define EIGUPD_SWITCH_K(kval, fn, ...)            \
+  switch (kval) {                                 \
+    case 1: return fn<1>(__VA_ARGS__);            \
+    case 2: return fn<2>(__VA_ARGS__);            \
+    case 3: return fn<3>(__VA_ARGS__);            \
+    case 4: return fn<4>(__VA_ARGS__);            \
+    case 5: return fn<5>(__VA_ARGS__);            \
+    case 6: return fn<6>(__VA_ARGS__);            \
+    case 7: return fn<7>(__VA_ARGS__);            \
+    case 8: return fn<8>(__VA_ARGS__);            \
+    default: return hipErrorInvalidValue;         \
+  }
+
+// One instance of the grouped FP64 product C = A B (all n x n, leading
+// dimension n); vec: 16-byte accesses allowed (n even, aligned pointers).
+struct GemmDesc {
+  const double* A;
+  const double* B;
+  double* C;
+  const int32_t* status;
+  int n;
+  int vec;
+};
+
 // Launchers (stream-ordered, no allocation).
 hipError_t launch_qtk(const Work& w, hipStream_t s);
 hipError_t launch_deflate(const Work& w, hipStream_t s);
 hipError_t launch_polecount(const Work& w, hipStream_t s);
 hipError_t launch_locate(const Work& w, hipStream_t s);
 hipError_t launch_rootsolve(const Work& w, hipStream_t s);
-hipError_t launch_finalize(const Work& w, double* lam_dst, hipStream_t s);
+hipError_t launch_finalize(const Work& w, hipStream_t s);
 hipError_t launch_wbuild(const Work& w, hipStream_t s);
 hipError_t launch_group_reflect(const Work& w, hipStream_t s);
 hipError_t launch_commit(const Work& w, hipStream_t s);
 // C = A * B, column-major, FP64 MFMA.  Skipped on the device when *status != 0.
 hipError_t launch_dgemm(int M, int N, int Kd, const double* A, int lda, const double* B, int ldb,
                         double* C, int ldc, const int32_t* status, hipStream_t s);
+// Grouped launches over `ninst` instances of one rank k (blocks = total blocks,
+// Group.prefix built from the per-instance counts below).
+int qtk_blocks(int n, int k);
+int root_blocks(int n);
+int wbuild_blocks(int n);
+int reflect_blocks(int n);
+int gemm_tiles(int n, int bt);
+hipError_t launch_qtk_group(int k, const Group& g, int blocks, hipStream_t s);
+hipError_t launch_deflate_group(int k, const Work* works, int ninst, hipStream_t s);
+hipError_t launch_polecount_group(int k, const Group& g, int blocks, hipStream_t s);
+hipError_t launch_locate_group(const Work* works, int ninst, hipStream_t s);
+// persistent_grid > 0: that many blocks draw (instance, root block) items from
+// *queue (reset on the stream first); 0: one block per item.
+hipError_t launch_rootsolve_group(int k, const Group& g, int blocks, int persistent_grid,
+                                  int* queue, hipStream_t s);
+hipError_t launch_finalize_group(int k, const Work* works, int ninst, hipStream_t s);
+hipError_t launch_wbuild_group(int k, const Group& g, int blocks, hipStream_t s);
+hipError_t launch_reflect_group(int k, const Group& g, int blocks, hipStream_t s);
+hipError_t launch_commit_group(const Work* works, int ninst, hipStream_t s);
+// bt = 128 or 64 (tile side); blocks = sum of gemm_tiles(n_i, bt)
+hipError_t launch_dgemm_group(int bt, const GemmDesc* d, const int* prefix, int ninst, int blocks,
+                              hipStream_t s);
+
 // Reduced-precision variants (prec = EIG_GEMM_FP32_CORR or EIG_GEMM_BF16X3_CORR):
 // U = Q^T K with the FP64 residual correction, and C = A * B on the matrix cores.
 hipError_t launch_qtk_lp(const Work& w, int prec, hipStream_t s);

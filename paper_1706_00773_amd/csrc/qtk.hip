@@ -11,10 +11,10 @@
 namespace eigupd {
 
 template <int K, int CPB>
-__global__ __launch_bounds__(256) void qtk_kernel(Work w) {
+__device__ __forceinline__ void qtk_body(const Work& w, int bid) {
   if (update_cancelled(w.st)) return;
   const int n = w.n;
-  const int j0 = blockIdx.x * CPB;
+  const int j0 = bid * CPB;
   double acc[CPB][K];
 #pragma unroll
   for (int q = 0; q < CPB; ++q)
@@ -55,11 +55,32 @@ __global__ __launch_bounds__(256) void qtk_kernel(Work w) {
   }
 }
 
+template <int K, int CPB>
+__global__ __launch_bounds__(256) void qtk_kernel(Work w) {
+  qtk_body<K, CPB>(w, blockIdx.x);
+}
+
+template <int K, int CPB>
+__global__ __launch_bounds__(256) void qtk_group(Group g) {
+  const int i = group_instance(g, blockIdx.x);
+  qtk_body<K, CPB>(g.works[i], blockIdx.x - g.prefix[i]);
+}
+
+constexpr int qtk_cpb(int k) { return (k <= 2) ? 8 : 4; }
+
+int qtk_blocks(int n, int k) { return (n + qtk_cpb(k) - 1) / qtk_cpb(k); }
+
 template <int K>
 static hipError_t qtk_launch(const Work& w, hipStream_t s) {
-  constexpr int CPB = (K <= 2) ? 8 : 4;
+  constexpr int CPB = qtk_cpb(K);
   const int grid = (w.n + CPB - 1) / CPB;
   hipLaunchKernelGGL((qtk_kernel<K, CPB>), dim3(grid), dim3(256), 0, s, w);
+  return hipGetLastError();
+}
+
+template <int K>
+static hipError_t qtk_group_launch(const Group& g, int blocks, hipStream_t s) {
+  hipLaunchKernelGGL((qtk_group<K, qtk_cpb(K)>), dim3(blocks), dim3(256), 0, s, g);
   return hipGetLastError();
 }
 
@@ -75,6 +96,11 @@ hipError_t launch_qtk(const Work& w, hipStream_t s) {
     case 8: return qtk_launch<8>(w, s);
     default: return hipErrorInvalidValue;
   }
+}
+
+hipError_t launch_qtk_group(int k, const Group& g, int blocks, hipStream_t s) {
+  if (blocks <= 0) return hipSuccess;
+  EIGUPD_SWITCH_K(k, qtk_group_launch, g, blocks, s)
 }
 
 }  // namespace eigupd

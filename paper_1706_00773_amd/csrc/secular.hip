@@ -146,13 +146,13 @@ __device__ __forceinline__ void sweep(const double* __restrict__ rd, const doubl
 // Pole counts nu(d_s) for every segment s.
 // ---------------------------------------------------------------------------
 template <int K>
-__global__ __launch_bounds__(64 * Cfg<K>::WV) void polecount_kernel(Work w) {
+__device__ __forceinline__ void polecount_body(const Work& w, int bid) {
   constexpr int NS = Sym<K>::NS, WV = Cfg<K>::WV, RPB = Cfg<K>::RPB, TP = Cfg<K>::TP;
   __shared__ double s_part[WV][NS][RPB];
   __shared__ PoleTile<K, TP> s_tile[WV];
   if (update_cancelled(w.st)) return;
   const int n_s = w.info->n_s, n_d = w.info->n_d;
-  const int s0 = blockIdx.x * RPB;
+  const int s0 = bid * RPB;
   if (s0 >= n_s) return;
   const int lane = threadIdx.x & 63, slot = lane % RPB;
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -193,7 +193,7 @@ __global__ __launch_bounds__(64 * Cfg<K>::WV) void polecount_kernel(Work w) {
 // ---------------------------------------------------------------------------
 constexpr int LNT = 1024;
 
-__global__ __launch_bounds__(LNT) void locate_kernel(Work w) {
+__device__ __forceinline__ void locate_body(const Work& w) {
   __shared__ int shi[LNT / 64 + 1];
   __shared__ int s_carry;
   if (update_cancelled(w.st)) return;
@@ -243,7 +243,7 @@ enum { PH_FIRST = 0, PH_SOLVE = 1, PH_DONE = 2 };
 constexpr double STAG = 1e-9;
 
 template <int K>
-__global__ __launch_bounds__(64 * Cfg<K>::WV) void rootsolve_kernel(Work w) {
+__device__ __forceinline__ void rootsolve_body(const Work& w, int bid) {
   constexpr int NS = Sym<K>::NS, WV = Cfg<K>::WV, RPB = Cfg<K>::RPB, TP = Cfg<K>::TP;
   __shared__ double s_part[WV][2 * NS][RPB];
   __shared__ PoleTile<K, TP> s_tile[WV];
@@ -251,7 +251,7 @@ __global__ __launch_bounds__(64 * Cfg<K>::WV) void rootsolve_kernel(Work w) {
   __shared__ int s_any;
   if (update_cancelled(w.st)) return;
   const int n_d = w.info->n_d, n_s = w.info->n_s;
-  const int i0 = blockIdx.x * RPB;
+  const int i0 = bid * RPB;
   if (i0 >= n_d) return;
   const int lane = threadIdx.x & 63, slot = lane % RPB;
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -465,7 +465,7 @@ __global__ __launch_bounds__(64 * Cfg<K>::WV) void rootsolve_kernel(Work w) {
 constexpr double CLUSTER_TOL = 1e-8;
 
 template <int K>
-__global__ __launch_bounds__(64 * Cfg<K>::WV) void rootvec_kernel(Work w) {
+__device__ __forceinline__ void rootvec_body(const Work& w, int bid) {
   constexpr int NS = Sym<K>::NS, WV = Cfg<K>::WV, RPB = Cfg<K>::RPB, TP = Cfg<K>::TP;
   constexpr int SPLIT = Cfg<K>::SPLIT;
   __shared__ double s_part[WV][2 * NS][RPB];
@@ -476,7 +476,7 @@ __global__ __launch_bounds__(64 * Cfg<K>::WV) void rootvec_kernel(Work w) {
   __shared__ int s_mc[RPB], s_pos[RPB], s_cluster;
   if (update_cancelled(w.st)) return;
   const int n_d = w.info->n_d, n_s = w.info->n_s;
-  const int i0 = blockIdx.x * RPB;
+  const int i0 = bid * RPB;
   if (i0 >= n_d) return;
   const int lane = threadIdx.x & 63, slot = lane % RPB;
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -693,6 +693,108 @@ __global__ __launch_bounds__(64 * Cfg<K>::WV) void rootvec_kernel(Work w) {
 #pragma unroll
   for (int c = 0; c < K; ++c) w.root_c[(size_t)i * K + c] = out[c];
   w.root_tv[i] = tau;
+}
+
+// ---------------------------------------------------------------------------
+// Kernels: one instance (Work by value), a group of instances of one rank
+// (Group), and the persistent root solver that takes (instance, root block)
+// items from a queue.
+// ---------------------------------------------------------------------------
+template <int K>
+__global__ __launch_bounds__(64 * Cfg<K>::WV) void polecount_kernel(Work w) {
+  polecount_body<K>(w, blockIdx.x);
+}
+template <int K>
+__global__ __launch_bounds__(64 * Cfg<K>::WV) void polecount_group(Group g) {
+  const int i = group_instance(g, blockIdx.x);
+  polecount_body<K>(g.works[i], blockIdx.x - g.prefix[i]);
+}
+
+__global__ __launch_bounds__(LNT) void locate_kernel(Work w) { locate_body(w); }
+__global__ __launch_bounds__(LNT) void locate_group(const Work* __restrict__ works) {
+  locate_body(works[blockIdx.x]);
+}
+
+template <int K>
+__global__ __launch_bounds__(64 * Cfg<K>::WV) void rootsolve_kernel(Work w) {
+  rootsolve_body<K>(w, blockIdx.x);
+}
+template <int K>
+__global__ __launch_bounds__(64 * Cfg<K>::WV) void rootsolve_group(Group g) {
+  const int i = group_instance(g, blockIdx.x);
+  rootsolve_body<K>(g.works[i], blockIdx.x - g.prefix[i]);
+}
+// A fixed grid of blocks; each takes the next item of the queue (an atomic
+// counter that starts at 0) until all `total` items are taken.  Every block
+// leaves the loop once the counter has passed `total`.
+template <int K>
+__global__ __launch_bounds__(64 * Cfg<K>::WV) void rootsolve_persist(Group g, int total,
+                                                                      int* queue) {
+  __shared__ int s_item;
+  for (;;) {
+    __syncthreads();
+    if (threadIdx.x == 0) s_item = atomicAdd(queue, 1);
+    __syncthreads();
+    const int item = s_item;
+    if (item >= total) break;
+    const int i = group_instance(g, item);
+    rootsolve_body<K>(g.works[i], item - g.prefix[i]);
+  }
+}
+
+template <int K>
+__global__ __launch_bounds__(64 * Cfg<K>::WV) void rootvec_kernel(Work w) {
+  rootvec_body<K>(w, blockIdx.x);
+}
+template <int K>
+__global__ __launch_bounds__(64 * Cfg<K>::WV) void rootvec_group(Group g) {
+  const int i = group_instance(g, blockIdx.x);
+  rootvec_body<K>(g.works[i], blockIdx.x - g.prefix[i]);
+}
+
+int root_blocks(int n) { return (n + 31) / 32; }
+
+template <int K>
+static hipError_t polecount_group_launch(const Group& g, int blocks, hipStream_t s) {
+  static_assert(Cfg<K>::RPB == 32, "root_blocks assumes 32 roots per block");
+  hipLaunchKernelGGL((polecount_group<K>), dim3(blocks), dim3(64 * Cfg<K>::WV), 0, s, g);
+  return hipGetLastError();
+}
+
+template <int K>
+static hipError_t rootsolve_group_launch(const Group& g, int blocks, int persistent_grid,
+                                         int* queue, hipStream_t s) {
+  hipError_t e;
+  if (persistent_grid > 0) {
+    hipLaunchKernelGGL(zero_ints_kernel, dim3(1), dim3(64), 0, s, queue, 1);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((rootsolve_persist<K>), dim3(min(persistent_grid, blocks)),
+                       dim3(64 * Cfg<K>::WV), 0, s, g, blocks, queue);
+  } else {
+    hipLaunchKernelGGL((rootsolve_group<K>), dim3(blocks), dim3(64 * Cfg<K>::WV), 0, s, g);
+  }
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((rootvec_group<K>), dim3(blocks), dim3(64 * Cfg<K>::WV), 0, s, g);
+  return hipGetLastError();
+}
+
+hipError_t launch_polecount_group(int k, const Group& g, int blocks, hipStream_t s) {
+  if (blocks <= 0) return hipSuccess;
+  EIGUPD_SWITCH_K(k, polecount_group_launch, g, blocks, s)
+}
+
+hipError_t launch_locate_group(const Work* works, int ninst, hipStream_t s) {
+  if (ninst <= 0) return hipSuccess;
+  hipLaunchKernelGGL(locate_group, dim3(ninst), dim3(LNT), 0, s, works);
+  return hipGetLastError();
+}
+
+hipError_t launch_rootsolve_group(int k, const Group& g, int blocks, int persistent_grid,
+                                  int* queue, hipStream_t s) {
+  if (blocks <= 0) return hipSuccess;
+  EIGUPD_SWITCH_K(k, rootsolve_group_launch, g, blocks, persistent_grid, queue, s)
 }
 
 template <int K>

@@ -43,7 +43,8 @@ __device__ __forceinline__ int count_less_equal(const double* v, int n, double x
 }
 
 template <int K>
-__global__ __launch_bounds__(FNT) void finalize_kernel(Work w, double* lam_dst) {
+__device__ __forceinline__ void finalize_body(const Work& w) {
+  double* lam_dst = w.lam_fin;
   __shared__ double s_carry;
   __shared__ double shd[FNT / 64];
   if (update_cancelled(w.st)) return;
@@ -103,13 +104,13 @@ __global__ __launch_bounds__(FNT) void finalize_kernel(Work w, double* lam_dst) 
   }
 }
 
-// W tile: 256 rows x CB columns per block.
+// W tile: 256 rows x CB columns per block (block coordinates bx, by).
 template <int K, int CB>
-__global__ __launch_bounds__(256) void wbuild_kernel(Work w) {
+__device__ __forceinline__ void wbuild_body(const Work& w, int bx, int by) {
   if (update_cancelled(w.st)) return;
   const int n = w.n;
-  const int r = blockIdx.x * 256 + threadIdx.x;
-  const int p0 = blockIdx.y * CB;
+  const int r = bx * 256 + threadIdx.x;
+  const int p0 = by * CB;
   const int pe = min(n, p0 + CB);
   if (r >= n) return;
   const int jr = w.rmap[r];
@@ -141,13 +142,13 @@ __global__ __launch_bounds__(256) void wbuild_kernel(Work w) {
 // One wave per column; every merged group's rows are mapped back with
 // H_0 H_1 ... H_{h-1} (the last reflector first).
 template <int K>
-__global__ __launch_bounds__(256) void group_reflect_kernel(Work w) {
+__device__ __forceinline__ void group_reflect_body(const Work& w, int bid) {
   if (update_cancelled(w.st)) return;
   const int n_mg = w.info->n_groups;
   if (n_mg == 0) return;
   const int n = w.n;
   const int lane = threadIdx.x & 63;
-  const int p = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int p = bid * 4 + (threadIdx.x >> 6);
   if (p >= n) return;
   double* col = w.W + (size_t)p * n;
   for (int gi = 0; gi < n_mg; ++gi) {
@@ -164,37 +165,66 @@ __global__ __launch_bounds__(256) void group_reflect_kernel(Work w) {
   }
 }
 
-__global__ void commit_kernel(Work w) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) {
+__device__ __forceinline__ void commit_body(const Work& w) {
+  if (threadIdx.x == 0) {
     if (w.st->status == 0) w.st->gen += 1;
   }
 }
 
+constexpr int WB_CB = 32;  // W columns per wbuild block
+
 template <int K>
-static hipError_t finalize_launch(const Work& w, double* lam_dst, hipStream_t s) {
-  hipLaunchKernelGGL((finalize_kernel<K>), dim3(1), dim3(FNT), 0, s, w, lam_dst);
+__global__ __launch_bounds__(FNT) void finalize_kernel(Work w) {
+  finalize_body<K>(w);
+}
+template <int K>
+__global__ __launch_bounds__(FNT) void finalize_group(const Work* __restrict__ works) {
+  finalize_body<K>(works[blockIdx.x]);
+}
+template <int K, int CB>
+__global__ __launch_bounds__(256) void wbuild_kernel(Work w) {
+  wbuild_body<K, CB>(w, blockIdx.x, blockIdx.y);
+}
+template <int K, int CB>
+__global__ __launch_bounds__(256) void wbuild_group(Group g) {
+  const int i = group_instance(g, blockIdx.x);
+  const Work& w = g.works[i];
+  const int b = blockIdx.x - g.prefix[i];
+  const int gx = (w.n + 255) / 256;
+  wbuild_body<K, CB>(w, b % gx, b / gx);
+}
+template <int K>
+__global__ __launch_bounds__(256) void group_reflect_kernel(Work w) {
+  group_reflect_body<K>(w, blockIdx.x);
+}
+template <int K>
+__global__ __launch_bounds__(256) void group_reflect_group(Group g) {
+  const int i = group_instance(g, blockIdx.x);
+  group_reflect_body<K>(g.works[i], blockIdx.x - g.prefix[i]);
+}
+__global__ void commit_kernel(Work w) { commit_body(w); }
+__global__ void commit_group(const Work* __restrict__ works) { commit_body(works[blockIdx.x]); }
+
+__global__ void zero_ints_kernel(int* p, int count) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < count; i += gridDim.x * blockDim.x)
+    p[i] = 0;
+}
+
+int wbuild_blocks(int n) { return ((n + 255) / 256) * ((n + WB_CB - 1) / WB_CB); }
+int reflect_blocks(int n) { return (n + 3) / 4; }
+
+template <int K>
+static hipError_t finalize_launch(const Work& w, hipStream_t s) {
+  hipLaunchKernelGGL((finalize_kernel<K>), dim3(1), dim3(FNT), 0, s, w);
   return hipGetLastError();
 }
 
-hipError_t launch_finalize(const Work& w, double* lam_dst, hipStream_t s) {
-  switch (w.k) {
-    case 1: return finalize_launch<1>(w, lam_dst, s);
-    case 2: return finalize_launch<2>(w, lam_dst, s);
-    case 3: return finalize_launch<3>(w, lam_dst, s);
-    case 4: return finalize_launch<4>(w, lam_dst, s);
-    case 5: return finalize_launch<5>(w, lam_dst, s);
-    case 6: return finalize_launch<6>(w, lam_dst, s);
-    case 7: return finalize_launch<7>(w, lam_dst, s);
-    case 8: return finalize_launch<8>(w, lam_dst, s);
-    default: return hipErrorInvalidValue;
-  }
-}
+hipError_t launch_finalize(const Work& w, hipStream_t s) { EIGUPD_SWITCH_K(w.k, finalize_launch, w, s) }
 
 template <int K>
 static hipError_t wbuild_launch(const Work& w, hipStream_t s) {
-  constexpr int CB = 32;
-  dim3 grid((w.n + 255) / 256, (w.n + CB - 1) / CB);
-  hipLaunchKernelGGL((wbuild_kernel<K, CB>), grid, dim3(256), 0, s, w);
+  dim3 grid((w.n + 255) / 256, (w.n + WB_CB - 1) / WB_CB);
+  hipLaunchKernelGGL((wbuild_kernel<K, WB_CB>), grid, dim3(256), 0, s, w);
   return hipGetLastError();
 }
 
@@ -225,6 +255,42 @@ hipError_t launch_group_reflect(const Work& w, hipStream_t s) {
 
 hipError_t launch_commit(const Work& w, hipStream_t s) {
   hipLaunchKernelGGL(commit_kernel, dim3(1), dim3(64), 0, s, w);
+  return hipGetLastError();
+}
+
+// ----- grouped launches (one rank k per launch; commit covers all instances)
+
+template <int K>
+static hipError_t finalize_group_launch(const Work* works, int ninst, hipStream_t s) {
+  hipLaunchKernelGGL((finalize_group<K>), dim3(ninst), dim3(FNT), 0, s, works);
+  return hipGetLastError();
+}
+template <int K>
+static hipError_t wbuild_group_launch(const Group& g, int blocks, hipStream_t s) {
+  hipLaunchKernelGGL((wbuild_group<K, WB_CB>), dim3(blocks), dim3(256), 0, s, g);
+  return hipGetLastError();
+}
+template <int K>
+static hipError_t reflect_group_launch(const Group& g, int blocks, hipStream_t s) {
+  hipLaunchKernelGGL((group_reflect_group<K>), dim3(blocks), dim3(256), 0, s, g);
+  return hipGetLastError();
+}
+
+hipError_t launch_finalize_group(int k, const Work* works, int ninst, hipStream_t s) {
+  if (ninst <= 0) return hipSuccess;
+  EIGUPD_SWITCH_K(k, finalize_group_launch, works, ninst, s)
+}
+hipError_t launch_wbuild_group(int k, const Group& g, int blocks, hipStream_t s) {
+  if (blocks <= 0) return hipSuccess;
+  EIGUPD_SWITCH_K(k, wbuild_group_launch, g, blocks, s)
+}
+hipError_t launch_reflect_group(int k, const Group& g, int blocks, hipStream_t s) {
+  if (blocks <= 0) return hipSuccess;
+  EIGUPD_SWITCH_K(k, reflect_group_launch, g, blocks, s)
+}
+hipError_t launch_commit_group(const Work* works, int ninst, hipStream_t s) {
+  if (ninst <= 0) return hipSuccess;
+  hipLaunchKernelGGL(commit_group, dim3(ninst), dim3(64), 0, s, works);
   return hipGetLastError();
 }
 

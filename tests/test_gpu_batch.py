@@ -1,0 +1,227 @@
+"""GPU tests of batched updates (eig_update_batch): uneven instances (different
+n and k) updated together must give, state by state, bitwise the same
+eigenvalues and eigenvectors as the same updates applied one at a time with
+eig_update_rankk (the batch runs the same kernels on the same data; the tuning
+knobs only change how the work is distributed).  Graph replays are checked on
+every replay, with eager work and synchronisations in between.  The single
+path is itself pinned to the oracle by test_gpu_update.py; here one sanity
+check against the oracle is kept per instance.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_1706_00773_amd as eu
+from paper_1706_00773_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+SHAPES = [(64, 1), (200, 2), (333, 4), (1000, 8), (513, 3), (130, 2), (257, 2), (96, 1)]
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    eu.load_library()
+
+
+def _dev_colmajor(a):
+    import torch
+
+    return torch.from_numpy(np.ascontiguousarray(np.asarray(a).T)).to("cuda:0").t()
+
+
+def _make_pairs(shapes, seed):
+    """Two identical states per shape (one for the batch, one for single updates)."""
+    import torch
+
+    insts = []
+    for i, (n, k) in enumerate(shapes):
+        u = wl.random_small(n, k, seed=seed + 31 * i, knorm=1.5)
+        pair = []
+        for _ in range(2):
+            s = eu.EigState(n, 0)
+            s.upload(torch.from_numpy(u.lam).to("cuda:0"), _dev_colmajor(u.Q))
+            pair.append(s)
+        insts.append((u, pair[0], pair[1]))
+    return insts
+
+
+def _perturbations(shapes, rng):
+    out = []
+    for n, k in shapes:
+        K = rng.standard_normal((n, k)) / math.sqrt(n)
+        out.append((_dev_colmajor(K), wl.random_signs(k, rng), K))
+    return out
+
+
+def _read(s, n):
+    import torch
+
+    lo = torch.empty(n, dtype=torch.float64, device="cuda:0")
+    Qo = torch.empty((n, n), dtype=torch.float64, device="cuda:0").t()
+    info = s.query(lo, Qo)
+    return lo.cpu().numpy(), Qo.cpu().numpy(), info
+
+
+def _close(insts):
+    for _, a, b in insts:
+        a.close()
+        b.close()
+
+
+def _run_rounds(batch, insts, shapes, rounds, seed, check_oracle=False, between=None):
+    import torch
+
+    rng = np.random.default_rng(seed)
+    for r in range(rounds):
+        pert = _perturbations(shapes, rng)
+        lam_before = [(_read(a, u.lam.size)[:2]) for u, a, _ in insts] if check_oracle else None
+        batch.update([(a, Kt, sig) for (u, a, _), (Kt, sig, _) in zip(insts, pert)])
+        for (u, _, b), (Kt, sig, _) in zip(insts, pert):
+            b.update(Kt, sig)
+        torch.cuda.synchronize()
+        if between is not None:
+            between()
+        for i, ((u, a, b), (Kt, sig, K)) in enumerate(zip(insts, pert)):
+            n = u.lam.size
+            la, Qa, ia = _read(a, n)
+            lb, Qb, ib = _read(b, n)
+            assert np.array_equal(la, lb), (r, i)
+            assert np.array_equal(Qa, Qb), (r, i)
+            assert ia.generation == ib.generation == r + 1
+            if check_oracle:
+                l0, Q0 = lam_before[i]
+                ref, _, _ = oracle.update(l0, np.asfortranarray(Q0), K, sig, values_only=True)
+                U = oracle.qtk(np.asfortranarray(Q0), K)
+                scale = np.abs(l0).max() + float(np.sum(U * U))
+                assert np.abs(la - ref).max() <= 1e-10 * scale
+
+
+def test_uneven_batch_matches_single_updates():
+    print("case uneven batch, 8 instances", flush=True)
+    insts = _make_pairs(SHAPES, 500)
+    with eu.EigBatch(16, 0) as batch:
+        _run_rounds(batch, insts, SHAPES, 1, seed=9, check_oracle=True)
+    _close(insts)
+
+
+def test_graph_replays_match_every_time():
+    import torch
+
+    print("case graph replays", flush=True)
+    insts = _make_pairs(SHAPES, 700)
+    scratch = torch.randn(512, 512, dtype=torch.float64, device="cuda:0")
+
+    def eager():
+        # unrelated eager work and a synchronisation between replays
+        y = scratch @ scratch
+        float(y.sum())
+        torch.cuda.synchronize()
+
+    with eu.EigBatch(16, 0) as batch:
+        _run_rounds(batch, insts, SHAPES, 6, seed=10, between=eager)
+        # rounds 1-2 tune (one candidate each), round 3 runs direct, round 4
+        # captures the graph and launches it, rounds 5-6 replay it
+        assert batch.get(eu.EIG_KNOB_GRAPHS) == 1
+        assert batch.get(eu.EIG_STAT_GRAPH_LAUNCHES) >= 3
+        assert batch.get(eu.EIG_STAT_GRAPHS_CACHED) == 1
+    _close(insts)
+
+
+@pytest.mark.parametrize("root,tile,graphs", [
+    (eu.EIG_ROOTSOLVE_GROUPED, 64, 0),
+    (eu.EIG_ROOTSOLVE_PERSISTENT, 128, 0),
+    (eu.EIG_ROOTSOLVE_PERSISTENT, 64, 1),
+])
+def test_forced_knobs_are_bitwise_neutral(root, tile, graphs):
+    print(f"case knobs root={root} tile={tile} graphs={graphs}", flush=True)
+    shapes = SHAPES[:6]
+    insts = _make_pairs(shapes, 900)
+    with eu.EigBatch(8, 0) as batch:
+        batch.set(eu.EIG_KNOB_ROOTSOLVE, root)
+        batch.set(eu.EIG_KNOB_GEMM_TILE, tile)
+        batch.set(eu.EIG_KNOB_GRAPHS, graphs)
+        _run_rounds(batch, insts, shapes, 3, seed=11)
+        assert batch.get(eu.EIG_KNOB_ROOTSOLVE) == root
+        assert batch.get(eu.EIG_KNOB_GEMM_TILE) == tile
+    _close(insts)
+
+
+def test_values_only_batch():
+    import torch
+
+    print("case values-only batch", flush=True)
+    shapes = SHAPES[:5]
+    insts = _make_pairs(shapes, 1100)
+    rng = np.random.default_rng(12)
+    pert = _perturbations(shapes, rng)
+    with eu.EigBatch(8, 0) as batch:
+        batch.update([(a, Kt, sig) for (u, a, _), (Kt, sig, _) in zip(insts, pert)],
+                     eu.EIG_VALUES_ONLY)
+    for (u, _, b), (Kt, sig, _) in zip(insts, pert):
+        b.update(Kt, sig, eu.EIG_VALUES_ONLY)
+    for (u, a, b) in insts:
+        n = u.lam.size
+        la = torch.empty(n, dtype=torch.float64, device="cuda:0")
+        lb = torch.empty(n, dtype=torch.float64, device="cuda:0")
+        ia, ib = a.query(la), b.query(lb)
+        assert torch.equal(la, lb)
+        assert ia.generation == ib.generation == 0
+    _close(insts)
+
+
+def test_error_in_one_instance_stays_in_its_state():
+    print("case sticky error in one instance", flush=True)
+    shapes = SHAPES[:4]
+    insts = _make_pairs(shapes, 1300)
+    rng = np.random.default_rng(13)
+    pert = _perturbations(shapes, rng)
+    Kbad = np.array(pert[1][2])
+    Kbad[3, 0] = np.nan
+    pert[1] = (_dev_colmajor(Kbad), pert[1][1], Kbad)
+    with eu.EigBatch(8, 0) as batch:
+        batch.update([(a, Kt, sig) for (u, a, _), (Kt, sig, _) in zip(insts, pert)])
+    for i, ((u, a, b), (Kt, sig, _)) in enumerate(zip(insts, pert)):
+        if i == 1:
+            with pytest.raises(eu.EigError) as e:
+                _read(a, u.lam.size)
+            assert e.value.code == eu.EIG_ENONFINITE
+            continue
+        b.update(Kt, sig)
+        la, Qa, _ = _read(a, u.lam.size)
+        lb, Qb, _ = _read(b, u.lam.size)
+        assert np.array_equal(la, lb) and np.array_equal(Qa, Qb)
+    _close(insts)
+
+
+def test_batch_argument_errors():
+    print("case batch argument errors", flush=True)
+    insts = _make_pairs(SHAPES[:2], 1500)
+    rng = np.random.default_rng(14)
+    pert = _perturbations(SHAPES[:2], rng)
+    (u0, a0, _), (u1, a1, _) = insts
+    with eu.EigBatch(2, 0) as batch:
+        with pytest.raises(eu.EigError) as e:  # the same state twice
+            batch.update([(a0, pert[0][0], pert[0][1]), (a0, pert[0][0], pert[0][1])])
+        assert e.value.code == eu.EIG_EINVAL
+        with pytest.raises(eu.EigError) as e:  # more items than the context holds
+            batch.update([(a0, pert[0][0], pert[0][1]), (a1, pert[1][0], pert[1][1]),
+                          (insts[1][2], pert[1][0], pert[1][1])])
+        assert e.value.code == eu.EIG_EINVAL
+        with pytest.raises(eu.EigError) as e:  # a sigma entry that is not +-1
+            batch.update([(a1, pert[1][0], np.array([1, 0]))])
+        assert e.value.code == eu.EIG_EINVAL
+        with pytest.raises(eu.EigError) as e:
+            batch.update([(a0, pert[0][0], pert[0][1])], eu.EIG_HOST_INPUT)
+        assert e.value.code == eu.EIG_EUNSUPPORTED
+        with pytest.raises(eu.EigError):
+            batch.set(eu.EIG_KNOB_GEMM_TILE, 96)
+        # nothing was enqueued: both states are still at generation 0
+        assert a0.query().generation == 0 and a1.query().generation == 0
+    _close(insts)
