@@ -266,6 +266,105 @@ def batch_report(args, dev):
                                              out["batched_graph"]["ms_per_round"], 3)}
 
 
+def serve_report(args, dev):
+    """Serving: 64 resident decompositions, n log-uniform in [256, 8192] (lambda uniform
+    in [-1, 1], Haar Q), requests choosing a matrix uniformly, k from {1, 2, 4, 8},
+    K ~ N(0, 1/n), random signs, chained per matrix in arrival order.  First the
+    saturated throughput (all requests submitted at once), then Poisson arrivals at
+    0.5, 0.7 and 0.9 of it, with per-request latency (submit -> completion seen by the
+    scheduler) p50/p99."""
+    import torch
+
+    import paper_1706_00773_amd as eu
+    from paper_1706_00773_amd import workloads as wl
+
+    log = lambda *a: print(*a, file=sys.stderr, flush=True)
+    sizes = wl.serving_sizes(args.serve_matrices, 256, 8192, seed=1005)
+    rng = np.random.default_rng(2005)
+    nbytes = lambda n: ((n * n * 8 + 255) // 256) * 256
+    resident = sum(nbytes(n) for n in sizes)
+    arena = resident + (args.serve_transient_gib << 30)
+    log(f"[bench] serving: {len(sizes)} matrices (resident Q {resident / 2**30:.2f} GiB), "
+        f"arena {arena / 2**30:.2f} GiB")
+    srv = eu.EigServer(arena, max_batch=args.serve_batch, streams=args.serve_streams,
+                       max_k_doubles=args.serve_batch * 8192 * 8)
+    for n in sizes:
+        lam = torch.from_numpy(np.sort(rng.uniform(-1.0, 1.0, n))).to(dev)
+        Q = wl.orthogonal_from(wl.gaussian_square(n, rng), str(dev))
+        srv.add(lam, Q)
+        del Q
+    torch.cuda.synchronize()
+
+    def make_requests(count):
+        out = []
+        for _ in range(count):
+            m = int(rng.integers(0, len(sizes)))
+            n = sizes[m]
+            k = int(rng.choice([1, 2, 4, 8]))
+            out.append((m, np.asfortranarray(rng.standard_normal((n, k)) / math.sqrt(n)),
+                        wl.random_signs(k, rng)))
+        return out
+
+    def run(reqs, rate):
+        comps = []
+        t0 = time.perf_counter()
+        gaps = rng.exponential(1.0 / rate, len(reqs)) if rate else np.zeros(len(reqs))
+        arrive = np.cumsum(gaps)
+        base = len(run.ids)
+        for i, (m, K, sig) in enumerate(reqs):
+            if rate:
+                while time.perf_counter() - t0 < arrive[i]:
+                    pass
+            srv.submit(m, K, sig, base + i)
+            if i % 64 == 63:
+                comps += srv.poll()
+        srv.drain()
+        while True:
+            more = srv.poll()
+            if not more:
+                break
+            comps += more
+        assert len(comps) == len(reqs), (len(comps), len(reqs))
+        run.ids += [c["request_id"] for c in comps]
+        bad = sum(1 for c in comps if c["status"] != 0)
+        t_first = min(c["t_submit"] for c in comps)
+        t_last = max(c["t_done"] for c in comps)
+        lat = np.array([c["t_done"] - c["t_submit"] for c in comps]) * 1000.0
+        return {"requests": len(comps), "failed": bad,
+                "throughput_req_s": round(len(comps) / (t_last - t_first), 2),
+                "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 3),
+                               "p99": round(float(np.percentile(lat, 99)), 3),
+                               "mean": round(float(lat.mean()), 3)},
+                "mean_batch": round(float(np.mean([c["batch_size"] for c in comps])), 2)}
+    run.ids = []
+
+    log("[bench]   warmup (256 requests)")
+    run(make_requests(256), 0.0)
+    log(f"[bench]   saturated ({args.serve_requests} requests at once)")
+    sat = run(make_requests(args.serve_requests), 0.0)
+    out = {"saturated": sat}
+    for f in (0.5, 0.7, 0.9):
+        rate = f * sat["throughput_req_s"]
+        log(f"[bench]   Poisson arrivals at {f} x saturated = {rate:.1f} req/s")
+        r = run(make_requests(args.serve_requests), rate)
+        r["offered_req_s"] = round(rate, 2)
+        out[f"poisson_{f}"] = r
+    st = srv.stats()
+    srv.close()
+    flops = 2.0 * float(np.mean([n ** 3 for n in sizes]))
+    return {"workload": f"serving: {len(sizes)} resident decompositions, n log-uniform in "
+                        "[256, 8192], requests uniform over matrices, k from {1,2,4,8}, "
+                        "chained per matrix",
+            "n": sizes, "arena_gib": round(arena / 2**30, 2),
+            "resident_gib": round(resident / 2**30, 2),
+            "max_batch": args.serve_batch, "streams": args.serve_streams,
+            "mean_gemm_flop_per_request": flops,
+            "modes": out,
+            "server": {"batches": st["batches"], "mean_batch": round(st["mean_batch"], 2),
+                       "arena_peak_gib": round(st["arena_peak"] / 2**30, 2),
+                       "compactions": st["compactions"]}}
+
+
 def measured_traffic():
     """HBM bytes per launch of the GEMM from the rocprofv3 FETCH_SIZE / WRITE_SIZE runs
     recorded under profiles/, or None once gemm.hip differs from the measured source."""
@@ -303,6 +402,12 @@ def main():
                     help="report batched updates of this many uneven instances")
     ap.add_argument("--batch-lo", type=int, default=256)
     ap.add_argument("--batch-hi", type=int, default=2048)
+    ap.add_argument("--serve", action="store_true", help="report the serving loop")
+    ap.add_argument("--serve-matrices", type=int, default=64)
+    ap.add_argument("--serve-requests", type=int, default=4096)
+    ap.add_argument("--serve-batch", type=int, default=32)
+    ap.add_argument("--serve-streams", type=int, default=2)
+    ap.add_argument("--serve-transient-gib", type=int, default=24)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (for HBM counter calibration)")
     args = ap.parse_args()
@@ -332,6 +437,9 @@ def main():
         return
     if args.batch:
         print(json.dumps(batch_report(args, dev)), flush=True)
+        return
+    if args.serve:
+        print(json.dumps(serve_report(args, dev)), flush=True)
         return
     n, k = args.n, args.k
     log = lambda *a: print(*a, file=sys.stderr, flush=True)

@@ -232,6 +232,83 @@ int eig_batch_get(eig_batch_t b, int32_t knob, int64_t *value);
 /* Release the context (after synchronising the device). */
 int eig_batch_destroy(eig_batch_t b);
 
+/* ------------------------------------------------------------------ serving
+ * A request loop over many resident decompositions.  Requests (matrix, k, K,
+ * sigma) are submitted from the host at any time; a scheduler thread admits
+ * them by device-memory footprint and runs them as batched updates
+ * (eig_update_batch) on several streams, starting a new batch on any stream
+ * whose previous batch has finished, so batches overlap on the device
+ * (continuous batching).  Updates of one matrix run in arrival order, one at a
+ * time, each on the decomposition its predecessor committed; a request's
+ * result is therefore the same as applying the same updates to that matrix
+ * alone.
+ *
+ * Memory: one device arena of arena_bytes holds every n x n buffer.  A
+ * resident matrix keeps its current Q there (8 n^2 bytes; lambda and O(n k)
+ * workspace live outside the arena); an admitted update borrows W and Q'
+ * (16 n^2 bytes) until it has finished, then the old Q (or, if the update
+ * failed, Q') and W are returned.  A request is admitted when both fit; the
+ * oldest waiting request is never overtaken while it waits for memory.  When
+ * requests wait with nothing running, the resident Q buffers are packed to
+ * one end of the arena first (their contents are moved on the device). */
+typedef struct eig_server_s *eig_server_t;
+
+typedef struct {
+  int64_t request_id; /* the caller's tag */
+  int32_t matrix;
+  int32_t status;     /* EIG_OK, or the error of this update (EIG_ENONFINITE,
+                         EIG_ENOCONV, EIG_ENOMEM if it could never fit, ...) */
+  double t_submit;    /* seconds since eig_server_create */
+  double t_admit;     /* its batch was enqueued */
+  double t_done;      /* the scheduler saw its batch finish */
+  int32_t batch_size; /* updates in that batch */
+  int32_t reserved;
+} eig_completion;
+
+typedef struct {
+  int64_t matrices, submitted, completed, failed, queued, in_flight, batches;
+  double mean_batch;                 /* updates per batch */
+  int64_t arena_bytes, resident_bytes, arena_used, arena_peak;
+  int64_t compactions;               /* times the resident buffers were packed */
+} eig_server_info;
+
+/* Create a server on `device`: an arena of arena_bytes, batches of at most
+ * max_batch updates, `streams` streams (1-8), and staging for at most
+ * max_k_doubles doubles of K per batch (a request needs n*k).
+ * Errors: EIG_EINVAL, EIG_EDEVICE, EIG_ENOMEM. */
+int eig_server_create(eig_server_t *out, int32_t device, int64_t arena_bytes, int32_t max_batch,
+                      int32_t streams, int64_t max_k_doubles);
+
+/* Register a decomposition (lambda ascending, Q n-by-n column-major, leading
+ * dimension ldq; device pointers if ptrs_on_device).  Copied; synchronous.
+ * *matrix receives its id (0, 1, ...).  Errors: EIG_EINVAL, EIG_ENOTSORTED,
+ * EIG_ENOMEM (its Q plus one update of the largest matrix would not fit). */
+int eig_server_add(eig_server_t s, int64_t n, const double *lambda, const double *Q, int64_t ldq,
+                   int32_t ptrs_on_device, int32_t *matrix);
+
+/* Queue A' = A + K diag(sigma) K^T for `matrix` (K on the host, n-by-k,
+ * leading dimension ldk; copied before return).  Errors: EIG_EINVAL,
+ * EIG_EUNSUPPORTED (k > EIG_KMAX). */
+int eig_server_submit(eig_server_t s, int32_t matrix, int64_t k, const double *K, int64_t ldk,
+                      const int8_t *sigma, int64_t request_id);
+
+/* Take up to max completions (waiting up to timeout_ms for the first). */
+int eig_server_poll(eig_server_t s, eig_completion *out, int32_t max, int32_t timeout_ms,
+                    int32_t *count);
+
+/* Wait until every submitted request has completed. */
+int eig_server_drain(eig_server_t s);
+
+/* Copy out a matrix's current decomposition after its queued updates have
+ * finished (waits for them). */
+int eig_server_read(eig_server_t s, int32_t matrix, double *lambda_out, double *Q_out,
+                    int64_t ldq, int32_t ptrs_on_device);
+
+int eig_server_stats(eig_server_t s, eig_server_info *info);
+
+/* Finish every queued request, then release everything. */
+int eig_server_destroy(eig_server_t s);
+
 /* Diagnostics: copy an intermediate of the last update to host memory `dst`
  * (`bytes` available) after synchronising `hip_stream`.  `what`:
  *   EIG_DBG_U            U = Q^T K, n-by-k row-major doubles

@@ -62,7 +62,9 @@ EIG_ROOTSOLVE_PERSISTENT = 2
 
 EXPORTED = ("eig_state_create", "eig_state_upload", "eig_update_rankk", "eig_query",
             "eig_state_destroy", "eig_status_str", "eig_debug_fetch", "eig_batch_create",
-            "eig_update_batch", "eig_batch_set", "eig_batch_get", "eig_batch_destroy")
+            "eig_update_batch", "eig_batch_set", "eig_batch_get", "eig_batch_destroy",
+            "eig_server_create", "eig_server_add", "eig_server_submit", "eig_server_poll",
+            "eig_server_drain", "eig_server_read", "eig_server_stats", "eig_server_destroy")
 
 
 class eig_info(ctypes.Structure):
@@ -96,6 +98,30 @@ class eig_batch_item(ctypes.Structure):
         ("ldk", ctypes.c_int64),
         ("sigma", ctypes.c_int8 * 8),
     ]
+
+
+class eig_completion(ctypes.Structure):
+    _fields_ = [
+        ("request_id", ctypes.c_int64),
+        ("matrix", ctypes.c_int32),
+        ("status", ctypes.c_int32),
+        ("t_submit", ctypes.c_double),
+        ("t_admit", ctypes.c_double),
+        ("t_done", ctypes.c_double),
+        ("batch_size", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
+    ]
+
+
+class eig_server_info(ctypes.Structure):
+    _fields_ = [(f, ctypes.c_int64) for f in ("matrices", "submitted", "completed", "failed",
+                                              "queued", "in_flight", "batches")] + [
+        ("mean_batch", ctypes.c_double)] + [
+        (f, ctypes.c_int64) for f in ("arena_bytes", "resident_bytes", "arena_used",
+                                      "arena_peak", "compactions")]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
 
 
 class EigError(RuntimeError):
@@ -132,6 +158,15 @@ def load_library(path: str = LIB_PATH):
     lib.eig_batch_set.argtypes = [vp, i32, i32]
     lib.eig_batch_get.argtypes = [vp, i32, ctypes.POINTER(i64)]
     lib.eig_batch_destroy.argtypes = [vp]
+    lib.eig_server_create.argtypes = [ctypes.POINTER(vp), i32, i64, i32, i32, i64]
+    lib.eig_server_add.argtypes = [vp, i64, vp, vp, i64, i32, ctypes.POINTER(i32)]
+    lib.eig_server_submit.argtypes = [vp, i32, i64, vp, i64, ctypes.POINTER(ctypes.c_int8), i64]
+    lib.eig_server_poll.argtypes = [vp, ctypes.POINTER(eig_completion), i32, i32,
+                                    ctypes.POINTER(i32)]
+    lib.eig_server_drain.argtypes = [vp]
+    lib.eig_server_read.argtypes = [vp, i32, vp, vp, i64, i32]
+    lib.eig_server_stats.argtypes = [vp, ctypes.POINTER(eig_server_info)]
+    lib.eig_server_destroy.argtypes = [vp]
     for name in EXPORTED:
         getattr(lib, name).restype = (ctypes.c_char_p if name == "eig_status_str"
                                       else ctypes.c_int)
@@ -329,6 +364,87 @@ class EigBatch:
     def close(self):
         if self.handle is not None:
             eig_batch_destroy(self.handle)
+            self.handle = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class EigServer:
+    """Serving loop over many resident decompositions (owns an eig_server_t)."""
+
+    def __init__(self, arena_bytes: int, max_batch: int = 32, streams: int = 2,
+                 max_k_doubles: int = 1 << 22, device: int = 0):
+        h = ctypes.c_void_p()
+        _check(load_library().eig_server_create(ctypes.byref(h), int(device), int(arena_bytes),
+                                                int(max_batch), int(streams),
+                                                int(max_k_doubles)), "eig_server_create")
+        self.handle = h
+        self._sizes = []
+
+    def add(self, lam, Q) -> int:
+        """Register (lam, Q); torch tensors on the GPU (Q column-major) or numpy arrays."""
+        n = lam.shape[0]
+        qp, ldq, qdev, qk = _colmajor_ptr(Q, n)
+        if _is_torch(lam):
+            lam_c = lam.contiguous()
+            lp = lam_c.data_ptr()
+        else:
+            lam_c = np.ascontiguousarray(lam, dtype=np.float64)
+            lp = lam_c.ctypes.data
+        mid = ctypes.c_int32()
+        _check(load_library().eig_server_add(self.handle, n, lp, qp, ldq, qdev,
+                                             ctypes.byref(mid)), "eig_server_add")
+        self._sizes.append(n)
+        return int(mid.value)
+
+    def submit(self, matrix: int, K, sigma, request_id: int):
+        """K: numpy n-by-k (host); copied before return."""
+        Kf = np.asfortranarray(np.asarray(K, dtype=np.float64).reshape(K.shape[0], -1))
+        k = Kf.shape[1]
+        sig = (ctypes.c_int8 * k)(*[int(v) for v in np.asarray(sigma).ravel()[:k]])
+        _check(load_library().eig_server_submit(self.handle, int(matrix), k, Kf.ctypes.data,
+                                                Kf.shape[0], sig, int(request_id)),
+               "eig_server_submit")
+
+    def poll(self, max_items: int = 1024, timeout_ms: int = 0):
+        buf = (eig_completion * max_items)()
+        cnt = ctypes.c_int32()
+        _check(load_library().eig_server_poll(self.handle, buf, max_items, int(timeout_ms),
+                                              ctypes.byref(cnt)), "eig_server_poll")
+        return [{f: getattr(buf[i], f) for f, _ in eig_completion._fields_}
+                for i in range(cnt.value)]
+
+    def drain(self):
+        _check(load_library().eig_server_drain(self.handle), "eig_server_drain")
+
+    def read(self, matrix: int):
+        """(lam, Q) of a matrix as numpy arrays (waits for its queued updates)."""
+        n = self._sizes[matrix]
+        lam = np.empty(n)
+        Q = np.empty((n, n), order="F")
+        _check(load_library().eig_server_read(self.handle, int(matrix), lam.ctypes.data,
+                                              Q.ctypes.data, n, 0), "eig_server_read")
+        return lam, Q
+
+    def stats(self):
+        info = eig_server_info()
+        _check(load_library().eig_server_stats(self.handle, ctypes.byref(info)),
+               "eig_server_stats")
+        return info.as_dict()
+
+    def close(self):
+        if self.handle is not None:
+            _check(load_library().eig_server_destroy(self.handle), "eig_server_destroy")
             self.handle = None
 
     def __enter__(self):

@@ -16,8 +16,8 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libeigupd.so")
 BUILD_DIR = os.path.join(ROOT, "_build")
 
-SOURCES = ["api.hip", "batch.hip", "qtk.hip", "deflate.hip", "secular.hip", "vectors.hip",
-           "gemm.hip", "precision.hip"]
+SOURCES = ["api.hip", "batch.hip", "server.hip", "qtk.hip", "deflate.hip", "secular.hip",
+           "vectors.hip", "gemm.hip", "precision.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -49,10 +49,16 @@ size_t carve(eig_state_s* s, void* base) {
   s->lam[0] = c.take<double>(n);
   s->lam[1] = c.take<double>(n);
   s->lam_vo = c.take<double>(n);
-  s->Q[0] = c.take<double>(n * n);
-  s->Q[1] = c.take<double>(n * n);
   Work& w = s->w;
-  w.W = c.take<double>(n * n);
+  if (s->lean) {
+    // Q and W buffers are lent per update by the owner of the state
+    s->Q[0] = s->Q[1] = nullptr;
+    w.W = nullptr;
+  } else {
+    s->Q[0] = c.take<double>(n * n);
+    s->Q[1] = c.take<double>(n * n);
+    w.W = c.take<double>(n * n);
+  }
   s->Kbuf = c.take<double>(n * KMAX);
   w.U = c.take<double>(n * KMAX);
   w.tiny = c.take<int>(n);
@@ -127,6 +133,14 @@ const char* eig_status_str(int status) {
 }
 
 int eig_state_create(eig_state_t* out, int64_t n, int32_t device) {
+  return eigupd::state_create(out, n, device, false);
+}
+
+}  // extern "C"
+
+namespace eigupd {
+
+int state_create(eig_state_t* out, int64_t n, int32_t device, bool lean) {
   if (!out || n < 1 || n > (int64_t)1 << 30) return EIG_EINVAL;
   *out = nullptr;
   int ndev = 0;
@@ -137,6 +151,7 @@ int eig_state_create(eig_state_t* out, int64_t n, int32_t device) {
   if (!s) return EIG_ENOMEM;
   s->device = device;
   s->n = n;
+  s->lean = lean;
   s->w.n = (int)n;
   const size_t bytes = carve(s, nullptr);
   void* block = nullptr;
@@ -167,6 +182,10 @@ int eig_state_create(eig_state_t* out, int64_t n, int32_t device) {
   return EIG_OK;
 }
 
+}  // namespace eigupd
+
+extern "C" {
+
 int eig_state_destroy(eig_state_t s) {
   if (!s) return EIG_EINVAL;
   {
@@ -183,7 +202,7 @@ int eig_state_destroy(eig_state_t s) {
 
 int eig_state_upload(eig_state_t s, const double* lambda, const double* Q, int64_t ldq,
                      int32_t ptrs_on_device, void* hip_stream) {
-  if (!s || !lambda || !Q || ldq < s->n) return EIG_EINVAL;
+  if (!s || !lambda || !Q || ldq < s->n || s->lean) return EIG_EINVAL;
   DeviceGuard g(s->device);
   if (!g.ok) return EIG_EDEVICE;
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
@@ -214,7 +233,7 @@ int eig_state_upload(eig_state_t s, const double* lambda, const double* Q, int64
 
 int eig_update_rankk(eig_state_t s, int64_t k, const double* K, int64_t ldk, const int8_t* sigma,
                      uint32_t mode, void* hip_stream) {
-  if (!s || !K || !sigma || k < 1 || ldk < s->n) return EIG_EINVAL;
+  if (!s || !K || !sigma || k < 1 || ldk < s->n || s->lean) return EIG_EINVAL;
   if (k > EIG_KMAX) return EIG_EUNSUPPORTED;
   if (k > s->n) return EIG_EINVAL;
   const uint32_t known = EIG_GEMM_MASK | EIG_VALUES_ONLY | EIG_HOST_INPUT | EIG_PHASE_TIMING;

@@ -8,6 +8,7 @@
 struct eig_state_s {
   int device = 0;
   int64_t n = 0;
+  bool lean = false;      // Q[], W not owned: lent per update (serving)
   void* block = nullptr;
   size_t block_bytes = 0;
   double* lam[2] = {nullptr, nullptr};
@@ -26,6 +27,10 @@ struct eig_state_s {
 };
 
 namespace eigupd {
+
+// Creates a state; lean: without its own Q buffers and W (24 n^2 bytes fewer),
+// for an owner that lends them per update.
+int state_create(eig_state_t* out, int64_t n, int32_t device, bool lean);
 
 // Descriptor of one update of state s (rank k, device K with leading
 // dimension ldk, bit c of sig_pos_mask set <=> sigma_c = +1).  Reads the

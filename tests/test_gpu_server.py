@@ -1,0 +1,186 @@
+"""GPU tests of the serving loop (eig_server_*).
+
+The key property: a request's result is the same alone and in the mix.  Every
+matrix's requests, submitted interleaved with other matrices' requests (and
+with submissions spread over time, so batches form while others run), must
+leave that matrix bitwise where the same updates applied alone, one by one,
+with eig_update_rankk leave it (batched kernels compute the same numbers as
+single ones); the final eigenvalues are also checked against the oracle
+chained over the same updates, within the FP64 bar.  Admission by memory,
+per-request failures and the completion records are checked too.
+"""
+import math
+import time
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_1706_00773_amd as eu
+from paper_1706_00773_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    eu.load_library()
+
+
+def _mats(sizes, seed):
+    out = []
+    for i, n in enumerate(sizes):
+        u = wl.random_small(n, 1, seed=seed + 7 * i)
+        out.append((u.lam, np.asfortranarray(u.Q)))
+    return out
+
+
+def _requests(sizes, count, rng, bad=()):
+    reqs = []
+    for rid in range(count):
+        m = int(rng.integers(0, len(sizes)))
+        n = sizes[m]
+        k = int(min(n, rng.choice([1, 2, 4, 8])))
+        K = np.asfortranarray(rng.standard_normal((n, k)) / math.sqrt(n))
+        if rid in bad:
+            K[0, 0] = np.nan
+        reqs.append((rid, m, K, wl.random_signs(k, rng)))
+    return reqs
+
+
+def _alone(lam, Q, updates):
+    """The matrix's updates applied one at a time with eig_update_rankk."""
+    import torch
+
+    n = lam.size
+    with eu.EigState(n, 0) as s:
+        s.upload(torch.from_numpy(lam).to("cuda:0"),
+                 torch.from_numpy(np.ascontiguousarray(Q.T)).to("cuda:0").t())
+        for K, sig in updates:
+            s.update(torch.from_numpy(np.ascontiguousarray(K.T)).to("cuda:0").t(), sig)
+            try:
+                s.query()
+            except eu.EigError:
+                pass  # a failed update leaves the state at its last commit
+        lo = torch.empty(n, dtype=torch.float64, device="cuda:0")
+        Qo = torch.empty((n, n), dtype=torch.float64, device="cuda:0").t()
+        s.query(lo, Qo)
+        return lo.cpu().numpy(), Qo.cpu().numpy()
+
+
+def _serve(mats, reqs, arena, max_batch=8, streams=2, spread_s=0.0):
+    comps = []
+    with eu.EigServer(arena, max_batch=max_batch, streams=streams) as srv:
+        ids = [srv.add(lam, Q) for lam, Q in mats]
+        assert ids == list(range(len(mats)))
+        for i, (rid, m, K, sig) in enumerate(reqs):
+            srv.submit(m, K, sig, rid)
+            if spread_s and i % 4 == 3:
+                time.sleep(spread_s)
+            comps += srv.poll()
+        srv.drain()
+        comps += srv.poll()
+        finals = [srv.read(m) for m in range(len(mats))]
+        stats = srv.stats()
+    return comps, finals, stats
+
+
+def test_same_alone_and_in_the_mix():
+    print("case serving mix: 6 matrices, 60 requests", flush=True)
+    sizes = [64, 300, 128, 513, 200, 96]
+    mats = _mats(sizes, 40)
+    rng = np.random.default_rng(41)
+    reqs = _requests(sizes, 60, rng)
+    comps, finals, stats = _serve(mats, reqs, arena=1 << 30, spread_s=0.002)
+    assert len(comps) == 60 and all(c["status"] == eu.EIG_OK for c in comps)
+    assert stats["completed"] == 60 and stats["failed"] == 0 and stats["in_flight"] == 0
+    # completion records: ordered times; per matrix, completion follows arrival
+    by_id = {c["request_id"]: c for c in comps}
+    for c in comps:
+        assert c["t_submit"] <= c["t_admit"] <= c["t_done"]
+        assert 1 <= c["batch_size"] <= 8
+    for m in range(len(sizes)):
+        mine = [rid for rid, mm, _, _ in reqs if mm == m]
+        done_t = [by_id[r]["t_done"] for r in mine]
+        assert done_t == sorted(done_t)
+    assert stats["batches"] < 60  # requests were batched together
+    for m, (lam, Q) in enumerate(mats):
+        ups = [(K, sig) for rid, mm, K, sig in reqs if mm == m]
+        la, Qa = _alone(lam, Q, ups)
+        lf, Qf = finals[m]
+        assert np.array_equal(lf, la), m
+        assert np.array_equal(Qf, Qa), m
+        # the oracle chained over the same updates
+        l_ref, Q_ref = lam, Q
+        for K, sig in ups:
+            l_ref, Q_ref, _ = oracle.update(l_ref, Q_ref, K, sig)
+        scale = np.abs(l_ref).max() + 1.0
+        assert np.abs(lf - l_ref).max() <= 1e-10 * scale * max(1, len(ups))
+
+
+def test_admission_bounded_by_arena():
+    print("case admission by memory", flush=True)
+    sizes = [512, 256, 384]
+    mats = _mats(sizes, 60)
+    rng = np.random.default_rng(61)
+    reqs = _requests(sizes, 24, rng)
+    nn = lambda n: ((n * n * 8 + 255) // 256) * 256
+    resident = sum(nn(n) for n in sizes)
+    # room for exactly one update of the largest matrix at a time
+    arena = resident + 2 * nn(512)
+    comps, finals, stats = _serve(mats, reqs, arena=arena, max_batch=8, streams=2)
+    assert all(c["status"] == eu.EIG_OK for c in comps) and len(comps) == 24
+    assert stats["arena_peak"] <= arena
+    assert stats["arena_used"] == resident
+    print(f"  batches {stats['batches']} mean {stats['mean_batch']:.2f} compactions {stats['compactions']}", flush=True)
+    for m, (lam, Q) in enumerate(mats):
+        la, Qa = _alone(lam, Q, [(K, sig) for rid, mm, K, sig in reqs if mm == m])
+        assert np.array_equal(finals[m][0], la) and np.array_equal(finals[m][1], Qa)
+    # an arena that cannot hold one update next to the resident Q refuses the add
+    with eu.EigServer(nn(512) + nn(512), max_batch=4, streams=1) as srv:
+        with pytest.raises(eu.EigError) as e:
+            srv.add(*mats[0])
+        assert e.value.code == eu.EIG_ENOMEM
+
+
+def test_failed_request_is_isolated():
+    print("case failed request in a stream", flush=True)
+    sizes = [200, 150, 90]
+    mats = _mats(sizes, 80)
+    rng = np.random.default_rng(81)
+    reqs = _requests(sizes, 30, rng, bad={5, 17})
+    comps, finals, stats = _serve(mats, reqs, arena=1 << 28)
+    st = {c["request_id"]: c["status"] for c in comps}
+    assert st[5] == eu.EIG_ENONFINITE and st[17] == eu.EIG_ENONFINITE
+    assert all(v == eu.EIG_OK for r, v in st.items() if r not in (5, 17))
+    assert stats["failed"] == 2
+    for m, (lam, Q) in enumerate(mats):
+        ups = [(K, sig) for rid, mm, K, sig in reqs if mm == m]
+        la, Qa = _alone(lam, Q, ups)
+        assert np.array_equal(finals[m][0], la) and np.array_equal(finals[m][1], Qa)
+
+
+def test_server_argument_errors():
+    print("case server argument errors", flush=True)
+    mats = _mats([64], 90)
+    with eu.EigServer(1 << 24, max_batch=2, streams=1) as srv:
+        m = srv.add(*mats[0])
+        K = np.zeros((64, 2), order="F")
+        with pytest.raises(eu.EigError) as e:
+            srv.submit(m + 1, K, [1, 1], 0)
+        assert e.value.code == eu.EIG_EINVAL
+        with pytest.raises(eu.EigError) as e:
+            srv.submit(m, K, [1, 2], 0)
+        assert e.value.code == eu.EIG_EINVAL
+        with pytest.raises(eu.EigError) as e:
+            srv.submit(m, np.zeros((64, 9), order="F"), [1] * 9, 0)
+        assert e.value.code == eu.EIG_EUNSUPPORTED
+        lam_bad = mats[0][0][::-1].copy()
+        with pytest.raises(eu.EigError) as e:
+            srv.add(lam_bad, mats[0][1])
+        assert e.value.code == eu.EIG_ENOTSORTED
+        assert srv.stats()["submitted"] == 0
