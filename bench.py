@@ -396,6 +396,8 @@ def main():
     ap.add_argument("--load-input", metavar="NPZ",
                     help="read the resident decomposition from NPZ (written by --save-input) "
                          "instead of generating it")
+    ap.add_argument("--locate-residues", action="store_true",
+                    help="k = 2: locate roots by residue signs (EIG_LOCATE_RESIDUES)")
     ap.add_argument("--precision", action="store_true",
                     help="report the reduced-precision modes (use with --n 16384 --k 4)")
     ap.add_argument("--batch", type=int, default=0,
@@ -469,9 +471,10 @@ def main():
     stream = torch.cuda.current_stream()
     torch.cuda.synchronize()
 
+    umode = eu.EIG_LOCATE_RESIDUES if args.locate_residues else 0
     log(f"[bench] warmup {warm}")
     for s in range(warm):
-        state.update(perts[s][0], perts[s][1])
+        state.update(perts[s][0], perts[s][1], umode)
     state.query()
     torch.cuda.synchronize()
 
@@ -482,7 +485,7 @@ def main():
     e0.record(stream)
     for s in range(steps):
         K, sig = perts[warm + s]
-        state.update(K, sig)
+        state.update(K, sig, umode)
     e1.record(stream)
     torch.cuda.synchronize()
     info = state.query()
@@ -493,11 +496,12 @@ def main():
     # pass B: per-update latency and phase times (events recorded by the library on
     # the update's stream)
     log(f"[bench] timed latency pass: {steps} updates with phase events")
-    lat, phases = [], []
+    lat, phases, located = [], [], []
     for s in range(steps):
         K, sig = perts[warm + steps + s]
-        state.update(K, sig, eu.EIG_PHASE_TIMING)
+        state.update(K, sig, eu.EIG_PHASE_TIMING | umode)
         inf = state.query()
+        located.append(inf.located_by_residues)
         lat.append(inf.ms[7])
         phases.append(list(inf.ms))
     phases = np.array(phases)
@@ -551,6 +555,8 @@ def main():
         "phases_ms": phase_ms,
         "qtk_hbm_gbs": round(qtk_gbs, 1),
         "iters_mean": round(info.iters_mean, 3),
+        "location": ("residue signs (Alg. 1), %d of %d updates" % (sum(located), len(located))
+                     if args.locate_residues else "inertia pole counts"),
         "orth_sample_max": orth,
         "roofline": roofline,
     }

@@ -64,6 +64,8 @@ typedef struct {
                                 [2] pole counts and location, [3] root refinement and null
                                 vectors, [4] eigenvalue merge and W, [5] Q W, [6] commit,
                                 [7] whole update */
+  int32_t located_by_residues; /* 1 if the roots were located by residue signs */
+  int32_t reserved;
 } eig_info;
 
 /* Status codes. */
@@ -109,8 +111,15 @@ enum {
   EIG_VALUES_ONLY = 1 << 4, /* eigenvalues only: nothing is committed, eig_query
                                returns these values until the next update */
   EIG_HOST_INPUT = 1 << 6,  /* K is a host pointer (copied before return) */
-  EIG_PHASE_TIMING = 1 << 7 /* record HIP events between the phases on hip_stream;
-                               eig_query reports the times in eig_info.ms */
+  EIG_PHASE_TIMING = 1 << 7, /* record HIP events between the phases on hip_stream;
+                                eig_query reports the times in eig_info.ms */
+  EIG_LOCATE_RESIDUES = 1 << 8 /* k = 2: locate the roots by the signs of the
+                                  residues alpha_i (Sec. 2.2, eq. (2), Alg. 1a-1c)
+                                  instead of the inertia pole counts; taken only
+                                  when every pole is simple and every residue is
+                                  larger than its rounding bound, else the pole
+                                  counts run (eig_info.located_by_residues tells
+                                  which); ignored for k != 2 */
 };
 
 enum { EIG_KMAX = 8 };

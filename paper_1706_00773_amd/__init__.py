@@ -39,6 +39,7 @@ EIG_GEMM_MASK = 3
 EIG_VALUES_ONLY = 1 << 4
 EIG_HOST_INPUT = 1 << 6
 EIG_PHASE_TIMING = 1 << 7
+EIG_LOCATE_RESIDUES = 1 << 8
 EIG_KMAX = 8
 
 EIG_DBG_U = 1
@@ -83,6 +84,8 @@ class eig_info(ctypes.Structure):
         ("anorm_bound", ctypes.c_double),
         ("generation", ctypes.c_int64),
         ("ms", ctypes.c_double * 8),
+        ("located_by_residues", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
     ]
 
     def as_dict(self):

@@ -236,7 +236,8 @@ int eig_update_rankk(eig_state_t s, int64_t k, const double* K, int64_t ldk, con
   if (!s || !K || !sigma || k < 1 || ldk < s->n || s->lean) return EIG_EINVAL;
   if (k > EIG_KMAX) return EIG_EUNSUPPORTED;
   if (k > s->n) return EIG_EINVAL;
-  const uint32_t known = EIG_GEMM_MASK | EIG_VALUES_ONLY | EIG_HOST_INPUT | EIG_PHASE_TIMING;
+  const uint32_t known = EIG_GEMM_MASK | EIG_VALUES_ONLY | EIG_HOST_INPUT | EIG_PHASE_TIMING |
+                         EIG_LOCATE_RESIDUES;
   if (mode & ~known) return EIG_EUNSUPPORTED;
   const int prec = (int)(mode & EIG_GEMM_MASK);
   if (prec != EIG_GEMM_FP64 && prec != EIG_GEMM_FP32_CORR && prec != EIG_GEMM_BF16X3_CORR)
@@ -303,6 +304,7 @@ int eig_update_rankk(eig_state_t s, int64_t k, const double* K, int64_t ldk, con
   HIPCHK(mark(1));
   HIPCHK(launch_deflate(w, st));
   HIPCHK(mark(2));
+  if ((mode & EIG_LOCATE_RESIDUES) && k == 2) HIPCHK(launch_alpha_locate(w, st));
   HIPCHK(launch_polecount(w, st));
   HIPCHK(launch_locate(w, st));
   HIPCHK(mark(3));
@@ -388,6 +390,7 @@ int eig_query(eig_state_t s, double* lambda_out, double* Q_out, int64_t ldq,
       info->iters_mean = (di.n_d > 0) ? (double)di.it_sum / (double)di.n_d : 0.0;
       info->defl_backward_err = di.bwd;
       info->anorm_bound = di.ahat;
+      info->located_by_residues = di.loc_alpha;
     }
     info->generation = ds.gen;
     if (s->timed) {

@@ -280,6 +280,8 @@ __device__ __forceinline__ void deflate_body(const Work& w) {
     info->it_min = 0x7fffffff;
     info->it_max = 0;
     info->it_sum = 0;
+    info->alpha_bad = 0;
+    info->loc_alpha = 0;
   }
 }
 

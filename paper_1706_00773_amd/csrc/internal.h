@@ -52,6 +52,8 @@ struct DevInfo {    // written by the kernels of one update
   double ahat, fro2, lower, upper, bwd;
   int32_t it_min, it_max;
   long long it_sum;
+  int32_t alpha_bad;   // residue location: a residue too small to trust its sign
+  int32_t loc_alpha;   // 1: the pole counts came from the residue signs
 };
 
 struct ColParam {   // one output column of W
@@ -164,6 +166,10 @@ struct GemmDesc {
 hipError_t launch_qtk(const Work& w, hipStream_t s);
 hipError_t launch_deflate(const Work& w, hipStream_t s);
 hipError_t launch_polecount(const Work& w, hipStream_t s);
+// Rank 2 only: pole counts from the signs of the residues alpha_s (eq. (2)) and
+// the Courant-Weyl bounds; leaves info->loc_alpha = 0 (and the pole-count
+// kernel then runs) when a residue is too small for its sign to be certain.
+hipError_t launch_alpha_locate(const Work& w, hipStream_t s);
 hipError_t launch_locate(const Work& w, hipStream_t s);
 hipError_t launch_rootsolve(const Work& w, hipStream_t s);
 hipError_t launch_finalize(const Work& w, hipStream_t s);

@@ -151,6 +151,7 @@ __device__ __forceinline__ void polecount_body(const Work& w, int bid) {
   __shared__ double s_part[WV][NS][RPB];
   __shared__ PoleTile<K, TP> s_tile[WV];
   if (update_cancelled(w.st)) return;
+  if (w.info->loc_alpha) return;  // the residue signs located the roots
   const int n_s = w.info->n_s, n_d = w.info->n_d;
   const int s0 = bid * RPB;
   if (s0 >= n_s) return;
@@ -693,6 +694,160 @@ __device__ __forceinline__ void rootvec_body(const Work& w, int bid) {
 #pragma unroll
   for (int c = 0; c < K; ++c) w.root_c[(size_t)i * K + c] = out[c];
   w.root_tv[i] = tau;
+}
+
+
+// ---------------------------------------------------------------------------
+// Rank-2 location from residue signs (Sec. 2.2, Alg. 1a-1c; eq. (2)).
+//
+// alpha_s = -det [[0, u_s^T], [Sigma u_s, I + Sigma U^T D_s U]] with
+// U^T D_s U = sum_{j != s} u_j u_j^T / (d_j - d_s) = -T_s, the same pole sweep as
+// the pole counts.  An interval between consecutive poles holds an odd number
+// of roots exactly when the residues at its ends have the same sign (virtual
+// signs -1 below the first pole and +1 above the last), and the Courant-Weyl
+// bounds leave two candidates for the number of roots below pole s, s - 1 + q
+// and s + q (q = negative signs): the parity of the odd intervals up to s picks
+// one.  This is the count Alg. 1a/1b/1c produce, formed by a prefix sum
+// instead of a sequential scan.  Used only when every pole is simple and every
+// residue is larger than a bound on its rounding error; otherwise the pole-count
+// kernel runs.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void alpha_body(const Work& w, int bid) {
+  constexpr int K = 2;
+  constexpr int WV = Cfg<K>::WV, RPB = Cfg<K>::RPB, TP = Cfg<K>::TP, SPLIT = Cfg<K>::SPLIT;
+  __shared__ double s_part[WV][6][RPB];
+  __shared__ PoleTile<K, TP> s_tile[WV];
+  if (update_cancelled(w.st)) return;
+  const int n_s = w.info->n_s, n_d = w.info->n_d;
+  if (n_s != n_d) {  // a multi-row pole: the residue formula does not apply
+    if (bid == 0 && threadIdx.x == 0) atomicOr(&w.info->alpha_bad, 1);
+    return;
+  }
+  const int s0 = bid * RPB;
+  if (s0 >= n_s) return;
+  const int lane = threadIdx.x & 63, slot = lane % RPB;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int s = min(s0 + slot, n_s - 1);
+  const double d_s = w.rd[s];
+  const int chunk = (n_d + WV - 1) / WV;
+  const int jb = min(n_d, wv * chunk), je = min(n_d, jb + chunk);
+  // T = sum u_j u_j^T / (d_s - d_j) and, for the error bound, sum |u_j u_j^T| / |d_s - d_j|
+  double acc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  sweep_poles<K, TP, SPLIT>(w.rd, w.ru, jb, je, 0.0, d_s, s_tile[wv],
+                            [&](double r, const double (&u)[K]) {
+                              const double a = u[0] * r, b = u[1] * r;
+                              acc[0] = fma(u[0], a, acc[0]);
+                              acc[1] = fma(u[0], b, acc[1]);
+                              acc[2] = fma(u[1], b, acc[2]);
+                              acc[3] += fabs(u[0] * a);
+                              acc[4] += fabs(u[0] * b);
+                              acc[5] += fabs(u[1] * b);
+                            });
+  combine_parts<SPLIT>(acc);
+  if (lane < RPB) {
+#pragma unroll
+    for (int e = 0; e < 6; ++e) s_part[wv][e][slot] = acc[e];
+  }
+  __syncthreads();
+  if (wv != 0 || lane >= RPB || s0 + slot >= n_s) return;
+#pragma unroll
+  for (int e = 0; e < 6; ++e) {
+    double t = 0.0;
+    for (int q = 0; q < WV; ++q) t += s_part[q][e][slot];
+    acc[e] = t;
+  }
+  const double s1 = (w.sig_pos_mask & 1) ? 1.0 : -1.0, s2 = (w.sig_pos_mask & 2) ? 1.0 : -1.0;
+  const double u1 = w.ru[(size_t)s * K], u2 = w.ru[(size_t)s * K + 1];
+  // M = I - Sigma T (rows scaled by Sigma)
+  const double m11 = 1.0 - s1 * acc[0], m12 = -s1 * acc[1];
+  const double m21 = -s2 * acc[1], m22 = 1.0 - s2 * acc[2];
+  const double alpha = u1 * (s1 * u1 * m22 - s2 * u2 * m12) - u2 * (s1 * u1 * m21 - s2 * u2 * m11);
+  // rounding bound: the n-term sums and the 3 x 3 expansion
+  const double a1 = fabs(u1), a2 = fabs(u2);
+  const double bound = a1 * (a1 * (1.0 + acc[5]) + a2 * acc[4]) +
+                       a2 * (a1 * acc[4] + a2 * (1.0 + acc[3]));
+  const double tol = 4.0 * (double)(n_d + 8) * EPSU * bound;
+  if (!(fabs(alpha) > tol)) atomicOr(&w.info->alpha_bad, 1);
+  w.nu[s] = (alpha > 0.0) ? 1 : -1;
+}
+
+__global__ __launch_bounds__(64 * Cfg<2>::WV) void alpha_kernel(Work w) {
+  alpha_body(w, blockIdx.x);
+}
+
+// Pole counts from the residue signs: one block; inclusive prefix count of the
+// odd intervals, then the Courant-Weyl candidate with that parity.  Checks that
+// the counts rise by 0, 1 or 2 per interval and end at n_d; otherwise leaves
+// them to the pole-count kernel.
+__global__ __launch_bounds__(LNT) void alpha_scan_kernel(Work w) {
+  __shared__ int sh[LNT / 64 + 1];
+  __shared__ int s_carry, s_bad, s_prev, s_prev_next;
+  if (update_cancelled(w.st)) return;
+  const int n_s = w.info->n_s, n_d = w.info->n_d;
+  if (w.info->alpha_bad || n_s != n_d) return;
+  const int q = w.info->q;
+  if (threadIdx.x == 0) {
+    s_carry = 0;
+    s_bad = 0;
+    s_prev = -1;  // virtual sign below the first pole
+  }
+  __syncthreads();
+  // nu[] holds the residue signs on entry and the counts on exit; each chunk
+  // reads all its signs before any of them is overwritten, and the sign of the
+  // chunk's last pole is carried to the next chunk in s_prev
+  for (int base = 0; base < n_s; base += LNT) {
+    const int t = base + threadIdx.x;  // interval just below pole t
+    const int last = min(base + LNT, n_s) - 1;
+    int sg = 0, odd = 0;
+    if (t < n_s) {
+      sg = w.nu[t];
+      const int left = (t == base) ? s_prev : w.nu[t - 1];
+      odd = (left == sg) ? 1 : 0;
+    }
+    int tot = 0;
+    const int excl = block_excl_scan<LNT>(odd, sh, &tot);  // synchronises the block
+    const int incl = s_carry + excl + odd;                   // odd intervals among 0..t
+    if (t == last) s_prev_next = sg;
+    if (t < n_s) {
+      const int lo = t - 1 + q;
+      const int v = ((lo - incl) & 1) ? lo + 1 : lo;
+      w.nu[t] = v;
+      if (v < 0 || v > n_d) s_bad = 1;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      s_carry += tot;
+      s_prev = s_prev_next;
+    }
+    __syncthreads();
+  }
+  // the counts rise by 0, 1 or 2 per interval; the interval above the last pole
+  // holds n_d - nu(last) roots, an odd number exactly when the last residue is
+  // positive
+  for (int t = threadIdx.x; t < n_s; t += LNT) {
+    const int prev = (t == 0) ? 0 : w.nu[t - 1];
+    const int d = w.nu[t] - prev;
+    if (d < 0 || d > 2) s_bad = 1;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const int top = n_d - ((n_s > 0) ? w.nu[n_s - 1] : 0);
+    if (top < 0 || top > 2 || ((top & 1) != (s_prev > 0 ? 1 : 0))) s_bad = 1;
+    if (s_bad)
+      w.info->alpha_bad = 1;
+    else
+      w.info->loc_alpha = 1;
+  }
+}
+
+hipError_t launch_alpha_locate(const Work& w, hipStream_t s) {
+  if (w.k != 2) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(alpha_kernel, dim3((w.n + Cfg<2>::RPB - 1) / Cfg<2>::RPB),
+                     dim3(64 * Cfg<2>::WV), 0, s, w);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(alpha_scan_kernel, dim3(1), dim3(LNT), 0, s, w);
+  return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------

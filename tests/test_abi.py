@@ -43,9 +43,33 @@ def test_status_strings():
     assert eu.eig_status_str(123) == "unknown status"
 
 
-def test_info_struct_layout():
-    # int64 x7, int32 x2, double x3, int64, double[8]
-    assert ctypes.sizeof(eu.eig_info) == 7 * 8 + 2 * 4 + 3 * 8 + 8 + 8 * 8
+def _c_layout(struct, fields):
+    """sizeof and offsetof as the C compiler lays out `struct` from include/eigupd.h."""
+    import subprocess
+    import tempfile
+
+    inc = os.path.join(ROOT, "include")
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "eigupd.h"', "int main(void) {",
+             f'  printf("%zu\\n", sizeof({struct}));']
+    lines += [f'  printf("%zu\\n", offsetof({struct}, {f}));' for f in fields]
+    lines += ["  return 0;", "}"]
+    with tempfile.TemporaryDirectory() as d:
+        src, exe = os.path.join(d, "l.c"), os.path.join(d, "l")
+        with open(src, "w") as fh:
+            fh.write("\n".join(lines) + "\n")
+        subprocess.run(["gcc", "-I", inc, src, "-o", exe], check=True)
+        out = subprocess.run([exe], check=True, capture_output=True, text=True).stdout.split()
+    return [int(v) for v in out]
+
+
+@pytest.mark.parametrize("cls", ["eig_info", "eig_batch_item", "eig_completion",
+                                 "eig_server_info"])
+def test_struct_layouts_match_the_header(cls):
+    st = getattr(eu, cls)
+    names = [f for f, _ in st._fields_]
+    c = _c_layout(cls, names)
+    assert ctypes.sizeof(st) == c[0]
+    assert [getattr(st, f).offset for f in names] == c[1:]
 
 
 def test_create_rejects_bad_size_without_device():
