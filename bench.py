@@ -365,6 +365,54 @@ def serve_report(args, dev):
                        "compactions": st["compactions"]}}
 
 
+def interval_report(args, dev):
+    """Subsets of the spectrum (eig_update_interval) at the headline size: the
+    eigenpairs in [a, b) for a, b at quantiles of the resident eigenvalues, against
+    the full update; median of 5 synchronous calls each."""
+    import torch
+
+    import paper_1706_00773_amd as eu
+    from paper_1706_00773_amd import workloads as wl
+
+    n, k = args.n, args.k
+    u = wl.plain_rank2(n, seed=1000, device=str(dev), min_gap=1e-12) if k == 2 else \
+        wl.general_rankk(k, n=n, device=str(dev))
+    state = eu.EigState(n, 0)
+    lam_t = torch.from_numpy(u.lam).to(dev)
+    state.upload(lam_t, u.Q)
+    Kt, sig = make_perturbations(n, k, 1, seed=4000, dev=dev)[0]
+    out = {}
+
+    def timed(fn, reps=5):
+        ts = []
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            r = fn()
+            torch.cuda.synchronize()
+            ts.append(1000.0 * (time.perf_counter() - t0))
+        return float(np.median(ts)), r
+
+    full_ms, _ = timed(lambda: (state.update(Kt, sig), state.query()))
+    state.upload(lam_t, u.Q)
+    out["full_update_ms"] = round(full_ms, 3)
+    for frac in (0.001, 0.01, 0.1, 0.5):
+        lo = 0.5 - frac / 2
+        a = float(u.lam[int(lo * (n - 1))])
+        b = float(u.lam[int((lo + frac) * (n - 1))])
+        ms, (lam, V) = timed(lambda: state.interval(Kt, sig, a, b, m_max=int(frac * n) + 64))
+        ms_vo, (lam2, _) = timed(lambda: state.interval(Kt, sig, a, b, mode=eu.EIG_VALUES_ONLY,
+                                                        m_max=int(frac * n) + 64))
+        out[f"fraction_{frac}"] = {"m": int(lam.numel()), "ms": round(ms, 3),
+                                   "values_only_ms": round(ms_vo, 3),
+                                   "speedup_vs_full": round(full_ms / ms, 2)}
+    state.close()
+    return {"workload": f"subset of the spectrum of a rank-{k} update, n={n}: eigenpairs in "
+                        "[a, b) around the middle of the spectrum (eig_update_interval, "
+                        "synchronous), against a full update plus query",
+            "modes": out}
+
+
 def measured_traffic():
     """HBM bytes per launch of the GEMM from the rocprofv3 FETCH_SIZE / WRITE_SIZE runs
     recorded under profiles/, or None once gemm.hip differs from the measured source."""
@@ -404,6 +452,8 @@ def main():
                     help="report batched updates of this many uneven instances")
     ap.add_argument("--batch-lo", type=int, default=256)
     ap.add_argument("--batch-hi", type=int, default=2048)
+    ap.add_argument("--interval", action="store_true",
+                    help="report subsets of the spectrum (eig_update_interval)")
     ap.add_argument("--serve", action="store_true", help="report the serving loop")
     ap.add_argument("--serve-matrices", type=int, default=64)
     ap.add_argument("--serve-requests", type=int, default=4096)
@@ -442,6 +492,9 @@ def main():
         return
     if args.serve:
         print(json.dumps(serve_report(args, dev)), flush=True)
+        return
+    if args.interval:
+        print(json.dumps(interval_report(args, dev)), flush=True)
         return
     n, k = args.n, args.k
     log = lambda *a: print(*a, file=sys.stderr, flush=True)

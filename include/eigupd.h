@@ -160,6 +160,33 @@ int eig_state_upload(eig_state_t s, const double *lambda, const double *Q, int64
 int eig_update_rankk(eig_state_t s, int64_t k, const double *K, int64_t ldk,
                      const int8_t *sigma, uint32_t mode, void *hip_stream);
 
+/* A subset of the spectrum: the eigenpairs of A' = A + K Sigma K^T whose
+ * eigenvalues lie in [a, b), without changing the state (Sec. 2.1: when only
+ * the eigenvalues in an interval are of interest, the first sub-problem -- the
+ * count -- is enough; Sec. 3: a subset of eigenvectors, e.g. a null space, is
+ * much cheaper than a full decomposition).  The counts at a and b select the
+ * roots of the secular equation to refine; only those m roots are solved and
+ * V = Q W is an n x n by n x m product (2 n^2 m flops instead of 2 n^3).
+ *   k, K, ldk, sigma   as for eig_update_rankk (K a device pointer unless
+ *                      mode has EIG_HOST_INPUT)
+ *   a <= b             the interval (infinite ends allowed); eigenvalues within
+ *                      rounding of a or b may fall on either side
+ *   mode               optional EIG_VALUES_ONLY | EIG_HOST_INPUT |
+ *                      EIG_LOCATE_RESIDUES
+ *   lambda_out         device pointer, m_max doubles: the m eigenvalues, ascending
+ *   V_out              device pointer, n-by-m_max column-major, leading dimension
+ *                      ldv >= n: their unit eigenvectors (not used with
+ *                      EIG_VALUES_ONLY)
+ *   *m_out             m, the number of eigenvalues in [a, b)
+ * Synchronous: returns after the outputs are written.  If m > m_max nothing is
+ * written, *m_out is m and the call returns EIG_EINVAL (call again with room).
+ * Errors: as eig_update_rankk; a device error (non-finite input,
+ * non-convergence) is returned directly and cleared. */
+int eig_update_interval(eig_state_t s, int64_t k, const double *K, int64_t ldk,
+                        const int8_t *sigma, double a, double b, uint32_t mode,
+                        double *lambda_out, double *V_out, int64_t ldv, int64_t m_max,
+                        int64_t *m_out, void *hip_stream);
+
 /* Synchronise `hip_stream`, report any deferred error, and copy out the
  * committed decomposition: lambda_out (n values, ascending; may be NULL) and
  * Q_out (n-by-n column-major, leading dimension ldq >= n; may be NULL).

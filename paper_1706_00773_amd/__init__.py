@@ -61,7 +61,8 @@ EIG_AUTO = 0
 EIG_ROOTSOLVE_GROUPED = 1
 EIG_ROOTSOLVE_PERSISTENT = 2
 
-EXPORTED = ("eig_state_create", "eig_state_upload", "eig_update_rankk", "eig_query",
+EXPORTED = ("eig_state_create", "eig_state_upload", "eig_update_rankk", "eig_update_interval",
+            "eig_query",
             "eig_state_destroy", "eig_status_str", "eig_debug_fetch", "eig_batch_create",
             "eig_update_batch", "eig_batch_set", "eig_batch_get", "eig_batch_destroy",
             "eig_server_create", "eig_server_add", "eig_server_submit", "eig_server_poll",
@@ -152,6 +153,9 @@ def load_library(path: str = LIB_PATH):
     lib.eig_update_rankk.argtypes = [vp, i64, vp, i64, ctypes.POINTER(ctypes.c_int8),
                                      ctypes.c_uint32, vp]
     lib.eig_query.argtypes = [vp, vp, vp, i64, i32, ctypes.POINTER(eig_info), vp]
+    lib.eig_update_interval.argtypes = [vp, i64, vp, i64, ctypes.POINTER(ctypes.c_int8),
+                                        ctypes.c_double, ctypes.c_double, ctypes.c_uint32, vp, vp,
+                                        i64, i64, ctypes.POINTER(i64), vp]
     lib.eig_state_destroy.argtypes = [vp]
     lib.eig_status_str.argtypes = [ctypes.c_int]
     lib.eig_status_str.restype = ctypes.c_char_p
@@ -256,6 +260,40 @@ def eig_update_rankk(s, K, sigma, mode: int = EIG_GEMM_FP64, stream=None) -> Non
     st = _current_stream(stream) if (kdev or stream is not None) else None
     _check(load_library().eig_update_rankk(s, k, kp, ldk, sig, int(mode), st),
            "eig_update_rankk")
+
+
+def eig_update_interval(s, K, sigma, a: float, b: float, mode: int = 0, m_max: int = 0,
+                        stream=None):
+    """Eigenpairs of A' = A + K diag(sigma) K^T with eigenvalues in [a, b), without
+    changing the state.  K: n-by-k torch tensor on the GPU (or numpy, copied).
+    Returns (lam, V) as torch tensors on the GPU (V None with EIG_VALUES_ONLY); m_max
+    is the initial capacity (grown once if the interval holds more)."""
+    import torch
+
+    n = K.shape[0]
+    k = 1 if K.ndim == 1 else K.shape[1]
+    kp, ldk, kdev, keep = _colmajor_ptr(K, n)
+    if not kdev:
+        mode |= EIG_HOST_INPUT
+    sig = (ctypes.c_int8 * k)(*[int(v) for v in np.asarray(sigma).ravel()[:k]])
+    st = _current_stream(stream)
+    vo = bool(mode & EIG_VALUES_ONLY)
+    cap = max(int(m_max), 1)
+    lib = load_library()
+    for _ in range(2):
+        lam = torch.empty(cap, dtype=torch.float64, device="cuda")
+        V = None if vo else torch.empty((cap, n), dtype=torch.float64, device="cuda").t()
+        m = ctypes.c_int64()
+        rc = lib.eig_update_interval(s, k, kp, ldk, sig, float(a), float(b), int(mode),
+                                     lam.data_ptr(), None if vo else V.data_ptr(), n, cap,
+                                     ctypes.byref(m), st)
+        if rc == EIG_EINVAL and m.value > cap:
+            cap = int(m.value)
+            continue
+        _check(rc, "eig_update_interval")
+        mm = int(m.value)
+        return lam[:mm], (None if vo else V[:, :mm])
+    raise EigError(EIG_EINVAL, "eig_update_interval")
 
 
 def eig_query(s, lambda_out=None, Q_out=None, stream=None, want_info: bool = True):
@@ -479,6 +517,9 @@ class EigState:
 
     def query(self, lambda_out=None, Q_out=None, stream=None):
         return eig_query(self.handle, lambda_out, Q_out, stream)
+
+    def interval(self, K, sigma, a, b, mode: int = 0, m_max: int = 0, stream=None):
+        return eig_update_interval(self.handle, K, sigma, a, b, mode, m_max, stream)
 
     def fetch(self, what: int, count: int, dtype=np.float64, stream=None):
         return eig_debug_fetch(self.handle, what, count, dtype, stream)

@@ -2,6 +2,8 @@
 // management, argument checks and the stream-ordered launch sequence of one
 // rank-k update.  All device memory is allocated once, in eig_state_create.
 #include <math.h>
+
+#include <cmath>
 #include <stdlib.h>
 #include <string.h>
 
@@ -153,6 +155,7 @@ int state_create(eig_state_t* out, int64_t n, int32_t device, bool lean) {
   s->n = n;
   s->lean = lean;
   s->w.n = (int)n;
+  s->w.ncols = (int)n;
   const size_t bytes = carve(s, nullptr);
   void* block = nullptr;
   if (hipMalloc(&block, bytes) != hipSuccess) {
@@ -339,6 +342,83 @@ int eig_update_rankk(eig_state_t s, int64_t k, const double* K, int64_t ldk, con
   HIPCHK(mark(8));
   s->enq_gen += 1;
   s->last_vo = false;
+  return EIG_OK;
+}
+
+int eig_update_interval(eig_state_t s, int64_t k, const double* K, int64_t ldk,
+                        const int8_t* sigma, double a, double b, uint32_t mode,
+                        double* lambda_out, double* V_out, int64_t ldv, int64_t m_max,
+                        int64_t* m_out, void* hip_stream) {
+  if (!s || !K || !sigma || !m_out || k < 1 || ldk < s->n || s->lean) return EIG_EINVAL;
+  *m_out = 0;
+  if (k > EIG_KMAX) return EIG_EUNSUPPORTED;
+  if (k > s->n || std::isnan(a) || std::isnan(b) || !(a <= b) || m_max < 0) return EIG_EINVAL;
+  const uint32_t known = EIG_VALUES_ONLY | EIG_HOST_INPUT | EIG_LOCATE_RESIDUES;
+  if (mode & ~known) return EIG_EUNSUPPORTED;
+  const bool vo = (mode & EIG_VALUES_ONLY) != 0;
+  if (m_max > 0 && !lambda_out) return EIG_EINVAL;
+  if (!vo && m_max > 0 && (!V_out || ldv < s->n)) return EIG_EINVAL;
+  int mask = 0;
+  for (int64_t c = 0; c < k; ++c) {
+    if (sigma[c] == 1)
+      mask |= 1 << c;
+    else if (sigma[c] != -1)
+      return EIG_EINVAL;
+  }
+  if (!s->uploaded) return EIG_ESTATE;
+  DeviceGuard g(s->device);
+  if (!g.ok) return EIG_EDEVICE;
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  const size_t n = (size_t)s->n;
+  const double* Kd = K;
+  int64_t ldkd = ldk;
+  if (mode & EIG_HOST_INPUT) {
+    HIPCHK(hipMemcpy2DAsync(s->Kbuf, n * sizeof(double), K, (size_t)ldk * sizeof(double),
+                            n * sizeof(double), (size_t)k, hipMemcpyHostToDevice, st));
+    Kd = s->Kbuf;
+    ldkd = (int64_t)n;
+  }
+  Work w = make_work(s, (int)k, Kd, (int)ldkd, mask, true);
+  // phase 1: U, deflation, location, and the roots that fall in [a, b)
+  HIPCHK(launch_qtk(w, st));
+  HIPCHK(launch_deflate(w, st));
+  if ((mode & EIG_LOCATE_RESIDUES) && k == 2) HIPCHK(launch_alpha_locate(w, st));
+  HIPCHK(launch_polecount(w, st));
+  HIPCHK(launch_locate(w, st));
+  HIPCHK(launch_interval_count(w, a, b, st));
+  HIPCHK(hipStreamSynchronize(st));
+  DevState ds;
+  DevInfo di;
+  HIPCHK(hipMemcpy(&ds, s->w.st, sizeof(ds), hipMemcpyDeviceToHost));
+  HIPCHK(hipMemcpy(&di, s->w.info, sizeof(di), hipMemcpyDeviceToHost));
+  auto device_error = [&]() -> int {
+    // report a device error and clear it: the state keeps its committed pair
+    DevState z = ds;
+    z.status = 0;
+    if (hipMemcpy(s->w.st, &z, sizeof(z), hipMemcpyHostToDevice) != hipSuccess) return EIG_EDEVICE;
+    return status_from_bits(ds.status);
+  };
+  if (ds.status != 0) return device_error();
+  const int nr = di.r_hi - di.r_lo, ne = di.e_hi - di.e_lo;
+  const int64_t m = (int64_t)nr + ne;
+  *m_out = m;
+  if (m > m_max) return EIG_EINVAL;
+  s->last_k = (int)k;
+  if (m == 0) return EIG_OK;
+  // phase 2: those roots, their vectors, W (n x m) and V = Q W (2 n^2 m flops)
+  w.lam_fin = lambda_out;
+  w.ncols = (int)m;
+  HIPCHK(launch_rootsolve(w, st, nr));
+  HIPCHK(launch_finalize(w, st));
+  if (!vo) {
+    HIPCHK(launch_wbuild(w, st));
+    HIPCHK(launch_group_reflect(w, st));
+    HIPCHK(launch_dgemm((int)n, (int)m, (int)n, w.Q_in, (int)n, w.W, (int)n, V_out, (int)ldv,
+                        &w.st->status, st));
+  }
+  HIPCHK(hipStreamSynchronize(st));
+  HIPCHK(hipMemcpy(&ds, s->w.st, sizeof(ds), hipMemcpyDeviceToHost));
+  if (ds.status != 0) return device_error();
   return EIG_OK;
 }
 

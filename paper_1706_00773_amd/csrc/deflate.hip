@@ -282,6 +282,10 @@ __device__ __forceinline__ void deflate_body(const Work& w) {
     info->it_sum = 0;
     info->alpha_bad = 0;
     info->loc_alpha = 0;
+    info->r_lo = 0;
+    info->r_hi = n_d;
+    info->e_lo = 0;
+    info->e_hi = cd;
   }
 }
 

@@ -54,6 +54,8 @@ struct DevInfo {    // written by the kernels of one update
   long long it_sum;
   int32_t alpha_bad;   // residue location: a residue too small to trust its sign
   int32_t loc_alpha;   // 1: the pole counts came from the residue signs
+  int32_t r_lo, r_hi;  // roots of the reduced problem to solve (all: 0, n_d)
+  int32_t e_lo, e_hi;  // deflated eigenvalues to keep (all: 0, n_defl)
 };
 
 struct ColParam {   // one output column of W
@@ -66,6 +68,7 @@ struct ColParam {   // one output column of W
 
 struct Work {
   int n, k, ldk, sig_pos_mask;  // bit c of sig_pos_mask set <=> sigma_c = +1
+  int ncols, pad_;              // columns of W built (n, or the size of a subset)
   const double* lam_in;
   const double* Q_in;
   double* lam_out;
@@ -171,7 +174,12 @@ hipError_t launch_polecount(const Work& w, hipStream_t s);
 // kernel then runs) when a residue is too small for its sign to be certain.
 hipError_t launch_alpha_locate(const Work& w, hipStream_t s);
 hipError_t launch_locate(const Work& w, hipStream_t s);
-hipError_t launch_rootsolve(const Work& w, hipStream_t s);
+// Subset of the spectrum: sets info->r_lo/r_hi to the roots of the reduced
+// problem in [a, b) and info->e_lo/e_hi to the deflated eigenvalues in [a, b)
+// (after deflate, polecount and locate).
+hipError_t launch_interval_count(const Work& w, double a, double b, hipStream_t s);
+// nroots >= 0: grid for that many roots (starting at info->r_lo); default all n
+hipError_t launch_rootsolve(const Work& w, hipStream_t s, int nroots = -1);
 hipError_t launch_finalize(const Work& w, hipStream_t s);
 hipError_t launch_wbuild(const Work& w, hipStream_t s);
 hipError_t launch_group_reflect(const Work& w, hipStream_t s);

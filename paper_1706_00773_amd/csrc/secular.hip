@@ -252,8 +252,9 @@ __device__ __forceinline__ void rootsolve_body(const Work& w, int bid) {
   __shared__ int s_any;
   if (update_cancelled(w.st)) return;
   const int n_d = w.info->n_d, n_s = w.info->n_s;
-  const int i0 = bid * RPB;
-  if (i0 >= n_d) return;
+  const int r_lo = w.info->r_lo, r_hi = w.info->r_hi;  // the roots to solve
+  const int i0 = r_lo + bid * RPB;
+  if (i0 >= r_hi) return;
   const int lane = threadIdx.x & 63, slot = lane % RPB;
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int chunk = (n_d + WV - 1) / WV;
@@ -262,7 +263,7 @@ __device__ __forceinline__ void rootsolve_body(const Work& w, int bid) {
   // solver state, meaningful in lanes 0..RPB-1 of wave 0
   const int i = i0 + slot;
   const bool owner = (wv == 0) && (lane < RPB);
-  const bool valid = owner && (i < n_d);
+  const bool valid = owner && (i < r_hi);
   const int tgt = i + 1;
   int phase = valid ? PH_FIRST : PH_DONE;
   int t = 0, clo = 0, chi = 0, evals = 0, rows_below = 0;
@@ -477,14 +478,15 @@ __device__ __forceinline__ void rootvec_body(const Work& w, int bid) {
   __shared__ int s_mc[RPB], s_pos[RPB], s_cluster;
   if (update_cancelled(w.st)) return;
   const int n_d = w.info->n_d, n_s = w.info->n_s;
-  const int i0 = bid * RPB;
-  if (i0 >= n_d) return;
+  const int r_lo = w.info->r_lo, r_hi = w.info->r_hi;  // the solved roots
+  const int i0 = r_lo + bid * RPB;
+  if (i0 >= r_hi) return;
   const int lane = threadIdx.x & 63, slot = lane % RPB;
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int chunk = (n_d + WV - 1) / WV;
   const int jb = min(n_d, wv * chunk), je = min(n_d, jb + chunk);
   const bool owner = (wv == 0) && (lane < RPB);
-  const int i = min(i0 + slot, n_d - 1);
+  const int i = min(i0 + slot, r_hi - 1);
   if (owner) {
     // the cluster [cs, ce) around root i
     const int oi = w.root_o[i], ti = w.root_t[i];
@@ -494,15 +496,15 @@ __device__ __forceinline__ void rootvec_body(const Work& w, int bid) {
              fabs(ta - tb) <= CLUSTER_TOL * fmax(fabs(ta), fabs(tb));
     };
     int cs = i, ce = i + 1;
-    for (int j = i - 1; j >= max(0, i - (K - 1)); --j) {
+    for (int j = i - 1; j >= max(r_lo, i - (K - 1)); --j) {
       if (!close(j, j + 1)) break;
       cs = j;
     }
-    for (int j = i + 1; j < min(n_d, cs + K); ++j) {
+    for (int j = i + 1; j < min(r_hi, cs + K); ++j) {
       if (!close(j - 1, j)) break;
       ce = j + 1;
     }
-    const int m_c = (i0 + slot < n_d) ? ce - cs : 1;
+    const int m_c = (i0 + slot < r_hi) ? ce - cs : 1;
     s_mc[slot] = m_c;
     s_pos[slot] = i - cs;
     s_tau[slot] = w.root_tau[cs];
@@ -594,7 +596,7 @@ __device__ __forceinline__ void rootvec_body(const Work& w, int bid) {
     for (int e = 0; e < NS; ++e) s_part[wv][e][slot] = gram[e];
   }
   __syncthreads();
-  if (!owner || i0 + slot >= n_d) return;
+  if (!owner || i0 + slot >= r_hi) return;
 #pragma unroll
   for (int e = 0; e < NS; ++e) {
     double as = 0.0;
@@ -850,6 +852,116 @@ hipError_t launch_alpha_locate(const Work& w, hipStream_t s) {
   return hipGetLastError();
 }
 
+
+// ---------------------------------------------------------------------------
+// Counts for a subset of the spectrum (Sec. 2.1: only the eigenvalues in an
+// interval of interest; the first sub-problem, the count, decides which roots
+// lie there).  For x = a and x = b: nu_red(x) = #{d_j < x} + neg(S(x)) - p over
+// the reduced problem (S summed by the block, the inertia from its k x k
+// eigenvalues), or the pole count when x is a pole; plus the number of deflated
+// eigenvalues below x.  One block.
+// ---------------------------------------------------------------------------
+template <int K>
+__global__ __launch_bounds__(256) void interval_count_kernel(Work w, double a, double b) {
+  constexpr int NS = Sym<K>::NS;
+  __shared__ double s_red[4][2 * NS];
+  __shared__ int s_res[4];
+  if (update_cancelled(w.st)) return;
+  const int n_d = w.info->n_d, n_s = w.info->n_s, n_defl = w.info->n_defl;
+  const double xs[2] = {a, b};
+  double S[2][NS];
+#pragma unroll
+  for (int q = 0; q < 2; ++q)
+#pragma unroll
+    for (int e = 0; e < NS; ++e) S[q][e] = 0.0;
+  for (int j = threadIdx.x; j < n_d; j += 256) {
+    double u[K];
+#pragma unroll
+    for (int c = 0; c < K; ++c) u[c] = w.ru[(size_t)j * K + c];
+    const double dj = w.rd[j];
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const double r = recip(xs[q] - dj);
+#pragma unroll
+      for (int c1 = 0; c1 < K; ++c1)
+#pragma unroll
+        for (int c2 = c1; c2 < K; ++c2)
+          S[q][Sym<K>::at(c1, c2)] = fma(u[c1] * r, u[c2], S[q][Sym<K>::at(c1, c2)]);
+    }
+  }
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int q = 0; q < 2; ++q)
+#pragma unroll
+    for (int e = 0; e < NS; ++e) {
+      const double t = wave_sum(S[q][e]);
+      if (lane == 0) s_red[wv][q * NS + e] = t;
+    }
+  __syncthreads();
+  if (threadIdx.x < 2) {
+    const int q = threadIdx.x;
+    const double x = xs[q];
+    int red;  // roots of the reduced problem below x
+    if (!(x > -INFINITY)) {
+      red = 0;
+    } else if (!(x < INFINITY)) {
+      red = n_d;
+    } else {
+      // segments strictly below x, and whether x is a pole
+      int lo = 0, hi = n_s;
+      while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (w.rd[w.seg_start[mid]] < x)
+          lo = mid + 1;
+        else
+          hi = mid;
+      }
+      if (lo < n_s && w.rd[w.seg_start[lo]] == x) {
+        red = w.nu[lo];  // x is a pole: the pole count
+      } else {
+        double T[NS];
+#pragma unroll
+        for (int e = 0; e < NS; ++e)
+          T[e] = s_red[0][q * NS + e] + s_red[1][q * NS + e] + s_red[2][q * NS + e] +
+                 s_red[3][q * NS + e];
+#pragma unroll
+        for (int c = 0; c < K; ++c) T[Sym<K>::at(c, c)] -= ((w.sig_pos_mask >> c) & 1) ? 1.0 : -1.0;
+        const int below = (lo < n_s) ? w.seg_start[lo] : n_d;  // rows with d_j < x
+        red = below + neg_count<K>(T) - w.info->p;
+      }
+    }
+    red = min(max(red, 0), n_d);
+    // deflated eigenvalues strictly below x
+    int lo = 0, hi = n_defl;
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if (w.dval[mid] < x)
+        lo = mid + 1;
+      else
+        hi = mid;
+    }
+    s_res[2 * q] = red;
+    s_res[2 * q + 1] = lo;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    w.info->r_lo = s_res[0];
+    w.info->r_hi = max(s_res[0], s_res[2]);
+    w.info->e_lo = s_res[1];
+    w.info->e_hi = max(s_res[1], s_res[3]);
+  }
+}
+
+template <int K>
+static hipError_t interval_count_launch(const Work& w, double a, double b, hipStream_t s) {
+  hipLaunchKernelGGL((interval_count_kernel<K>), dim3(1), dim3(256), 0, s, w, a, b);
+  return hipGetLastError();
+}
+
+hipError_t launch_interval_count(const Work& w, double a, double b, hipStream_t s) {
+  EIGUPD_SWITCH_K(w.k, interval_count_launch, w, a, b, s)
+}
+
 // ---------------------------------------------------------------------------
 // Kernels: one instance (Work by value), a group of instances of one rank
 // (Group), and the persistent root solver that takes (instance, root block)
@@ -960,8 +1072,9 @@ static hipError_t polecount_launch(const Work& w, hipStream_t s) {
 }
 
 template <int K>
-static hipError_t rootsolve_launch(const Work& w, hipStream_t s) {
-  const int grid = (w.n + Cfg<K>::RPB - 1) / Cfg<K>::RPB;
+static hipError_t rootsolve_launch(const Work& w, int nroots, hipStream_t s) {
+  if (nroots <= 0) return hipSuccess;
+  const int grid = (nroots + Cfg<K>::RPB - 1) / Cfg<K>::RPB;
   hipLaunchKernelGGL((rootsolve_kernel<K>), dim3(grid), dim3(64 * Cfg<K>::WV), 0, s, w);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
@@ -984,7 +1097,9 @@ static hipError_t rootsolve_launch(const Work& w, hipStream_t s) {
 
 hipError_t launch_polecount(const Work& w, hipStream_t s) { EIGUPD_DISPATCH_K(polecount_launch) }
 
-hipError_t launch_rootsolve(const Work& w, hipStream_t s) { EIGUPD_DISPATCH_K(rootsolve_launch) }
+hipError_t launch_rootsolve(const Work& w, hipStream_t s, int nroots) {
+  EIGUPD_SWITCH_K(w.k, rootsolve_launch, w, nroots < 0 ? w.n : nroots, s)
+}
 
 hipError_t launch_locate(const Work& w, hipStream_t s) {
   hipLaunchKernelGGL(locate_kernel, dim3(1), dim3(LNT), 0, s, w);

@@ -42,20 +42,26 @@ __device__ __forceinline__ int count_less_equal(const double* v, int n, double x
   return lo;
 }
 
+// Merges the roots [r_lo, r_hi) of the reduced problem (made monotone by a
+// running maximum) with the deflated eigenvalues [e_lo, e_hi) (all of them for
+// a full update) into lam_fin[0 ..) and one ColParam per output column.
 template <int K>
 __device__ __forceinline__ void finalize_body(const Work& w) {
   double* lam_dst = w.lam_fin;
   __shared__ double s_carry;
   __shared__ double shd[FNT / 64];
   if (update_cancelled(w.st)) return;
-  const int n_d = w.info->n_d, n_defl = w.info->n_defl;
+  const int r_lo = w.info->r_lo, r_hi = w.info->r_hi;
+  const int e_lo = w.info->e_lo, e_hi = w.info->e_hi;
+  const double* dval = w.dval + e_lo;
+  const int n_e = e_hi - e_lo, n_r = r_hi - r_lo;
   if (threadIdx.x == 0) s_carry = -INFINITY;
   __syncthreads();
   // absolute root values, running maximum
-  for (int base = 0; base < n_d; base += FNT) {
+  for (int base = r_lo; base < r_hi; base += FNT) {
     const int i = base + threadIdx.x;
     double x = -INFINITY;
-    if (i < n_d) x = w.rd[w.seg_start[w.root_o[i]]] + w.root_tau[i];
+    if (i < r_hi) x = w.rd[w.seg_start[w.root_o[i]]] + w.root_tau[i];
     double v = wave_incl_max(x);
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     __syncthreads();
@@ -64,15 +70,15 @@ __device__ __forceinline__ void finalize_body(const Work& w) {
     double pre = s_carry;
     for (int q = 0; q < wv; ++q) pre = fmax(pre, shd[q]);
     v = fmax(v, pre);
-    if (i < n_d) w.xs[i] = v;
+    if (i < r_hi) w.xs[i] = v;
     __syncthreads();
     if (threadIdx.x == FNT - 1) s_carry = v;
     __syncthreads();
   }
   __syncthreads();
-  for (int i = threadIdx.x; i < n_d; i += FNT) {
+  for (int i = r_lo + threadIdx.x; i < r_hi; i += FNT) {
     const double x = w.xs[i];
-    const int pos = i + count_less(w.dval, n_defl, x);
+    const int pos = (i - r_lo) + count_less(dval, n_e, x);
     lam_dst[pos] = x;
     ColParam cp;
     const int o = w.root_o[i];
@@ -89,16 +95,16 @@ __device__ __forceinline__ void finalize_body(const Work& w) {
     cp.pad = 0;
     w.colp[pos] = cp;
   }
-  for (int j = threadIdx.x; j < n_defl; j += FNT) {
-    const double v = w.dval[j];
-    const int pos = j + count_less_equal(w.xs, n_d, v);
+  for (int j = threadIdx.x; j < n_e; j += FNT) {
+    const double v = dval[j];
+    const int pos = j + count_less_equal(w.xs + r_lo, n_r, v);
     lam_dst[pos] = v;
     ColParam cp;
     cp.d_o = 0.0;
     cp.tau = 0.0;
 #pragma unroll
     for (int c = 0; c < KMAX; ++c) cp.c[c] = 0.0;
-    cp.drow = w.drow[j];
+    cp.drow = w.drow[e_lo + j];
     cp.pad = 0;
     w.colp[pos] = cp;
   }
@@ -111,7 +117,7 @@ __device__ __forceinline__ void wbuild_body(const Work& w, int bx, int by) {
   const int n = w.n;
   const int r = bx * 256 + threadIdx.x;
   const int p0 = by * CB;
-  const int pe = min(n, p0 + CB);
+  const int pe = min(w.ncols, p0 + CB);
   if (r >= n) return;
   const int jr = w.rmap[r];
   double dj = 0.0, u[K];
@@ -149,7 +155,7 @@ __device__ __forceinline__ void group_reflect_body(const Work& w, int bid) {
   const int n = w.n;
   const int lane = threadIdx.x & 63;
   const int p = bid * 4 + (threadIdx.x >> 6);
-  if (p >= n) return;
+  if (p >= w.ncols) return;
   double* col = w.W + (size_t)p * n;
   for (int gi = 0; gi < n_mg; ++gi) {
     const int g = w.mg_list[gi];
@@ -223,14 +229,16 @@ hipError_t launch_finalize(const Work& w, hipStream_t s) { EIGUPD_SWITCH_K(w.k, 
 
 template <int K>
 static hipError_t wbuild_launch(const Work& w, hipStream_t s) {
-  dim3 grid((w.n + 255) / 256, (w.n + WB_CB - 1) / WB_CB);
+  if (w.ncols <= 0) return hipSuccess;
+  dim3 grid((w.n + 255) / 256, (w.ncols + WB_CB - 1) / WB_CB);
   hipLaunchKernelGGL((wbuild_kernel<K, WB_CB>), grid, dim3(256), 0, s, w);
   return hipGetLastError();
 }
 
 template <int K>
 static hipError_t group_reflect_launch(const Work& w, hipStream_t s) {
-  hipLaunchKernelGGL((group_reflect_kernel<K>), dim3((w.n + 3) / 4), dim3(256), 0, s, w);
+  if (w.ncols <= 0) return hipSuccess;
+  hipLaunchKernelGGL((group_reflect_kernel<K>), dim3((w.ncols + 3) / 4), dim3(256), 0, s, w);
   return hipGetLastError();
 }
 
