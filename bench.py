@@ -413,6 +413,83 @@ def interval_report(args, dev):
             "modes": out}
 
 
+def perturbation_sweep(args, dev):
+    """The accuracy experiment of the paper's Sec. 3 (Fig. 6, 7) on synthetic data: N = 100,
+    norm(K) in {0.01, 0.3}, rank k = 1..8, perturbation K K^T (all signs +1).  For the
+    direct FP64 eigendecomposition of A' (torch.linalg.eigh on the GPU), this library's
+    update, and the first-order perturbation estimate (eq. (11)): (A) 2-norm error of the
+    eigenvalues against the direct decomposition, (B) ||A' - V diag(lambda) V^T||_2,
+    (C) ||V^T V - I||_2, (D) time (median of 20; the update split into its values-only
+    part and the whole)."""
+    import torch
+
+    import paper_1706_00773_amd as eu
+    from paper_1706_00773_amd import workloads as wl
+
+    N = 100
+    rows = []
+
+    def med(fn, reps=20):
+        ts = []
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            out = fn()
+            torch.cuda.synchronize()
+            ts.append(1000.0 * (time.perf_counter() - t0))
+        return float(np.median(ts)), out
+
+    for norm in (0.01, 0.3):
+        for k in range(1, 9):
+            rng = np.random.default_rng(7000 + 10 * k + (norm > 0.1))
+            lam = np.sort(rng.uniform(-1.0, 1.0, N))
+            Q = wl.orthogonal_from(wl.gaussian_square(N, rng))
+            K = rng.standard_normal((N, k))
+            K *= norm / np.linalg.norm(K, 2)
+            sig = np.ones(k, dtype=np.int8)
+            A = (Q * lam) @ Q.T + K @ K.T
+            A = (A + A.T) / 2
+            At = torch.from_numpy(A).to(dev)
+            t_direct, (wd, Vd) = med(lambda: torch.linalg.eigh(At))
+            wd = wd.cpu().numpy()
+            Kt = torch.from_numpy(np.ascontiguousarray(K.T)).to(dev).t()
+            lam_t = torch.from_numpy(lam).to(dev)
+            Q_t = torch.from_numpy(np.ascontiguousarray(Q.T)).to(dev).t()
+            st = eu.EigState(N, 0)
+            lo = torch.empty(N, dtype=torch.float64, device=dev)
+            Qo = torch.empty((N, N), dtype=torch.float64, device=dev).t()
+
+            def upd(mode):
+                st.upload(lam_t, Q_t)
+                torch.cuda.synchronize()
+                st.update(Kt, sig, mode)
+                st.query(lo, Qo if not (mode & eu.EIG_VALUES_ONLY) else None)
+
+            t_vals, _ = med(lambda: upd(eu.EIG_VALUES_ONLY))
+            t_full, _ = med(lambda: upd(0))
+            lu, Vu = lo.cpu().numpy(), Qo.cpu().numpy()
+            t_pert, (lp, Vp) = med(lambda: st.perturb_first_order(Kt, sig))
+            lp, Vp = lp.cpu().numpy(), Vp.cpu().numpy()
+            st.close()
+
+            def metrics(l, V):
+                o = np.argsort(l)
+                l, V = l[o], V[:, o]
+                return {"A_eigenvalues": float(np.linalg.norm(l - wd)),
+                        "B_reconstruction": float(np.linalg.norm(A - (V * l) @ V.T, 2)),
+                        "C_orthogonality": float(np.linalg.norm(V.T @ V - np.eye(N), 2))}
+
+            rows.append({"norm_K": norm, "k": k,
+                         "direct": dict(metrics(wd, Vd.cpu().numpy()), ms=round(t_direct, 3)),
+                         "update": dict(metrics(lu, Vu), ms=round(t_full, 3),
+                                        values_only_ms=round(t_vals, 3)),
+                         "perturbation": dict(metrics(lp, Vp), ms=round(t_pert, 3))})
+    return {"workload": "accuracy experiment of Sec. 3 (Fig. 6/7) on synthetic data: N = 100, "
+                        "lambda uniform in [-1, 1], Haar Q, K Gaussian scaled to norm(K), "
+                        "perturbation K K^T, k = 1..8",
+            "rows": rows}
+
+
 def measured_traffic():
     """HBM bytes per launch of the GEMM from the rocprofv3 FETCH_SIZE / WRITE_SIZE runs
     recorded under profiles/, or None once gemm.hip differs from the measured source."""
@@ -454,6 +531,8 @@ def main():
     ap.add_argument("--batch-hi", type=int, default=2048)
     ap.add_argument("--interval", action="store_true",
                     help="report subsets of the spectrum (eig_update_interval)")
+    ap.add_argument("--perturbation-sweep", action="store_true",
+                    help="the N = 100 accuracy experiment against eq. (11)")
     ap.add_argument("--serve", action="store_true", help="report the serving loop")
     ap.add_argument("--serve-matrices", type=int, default=64)
     ap.add_argument("--serve-requests", type=int, default=4096)
@@ -495,6 +574,9 @@ def main():
         return
     if args.interval:
         print(json.dumps(interval_report(args, dev)), flush=True)
+        return
+    if args.perturbation_sweep:
+        print(json.dumps(perturbation_sweep(args, dev)), flush=True)
         return
     n, k = args.n, args.k
     log = lambda *a: print(*a, file=sys.stderr, flush=True)

@@ -187,6 +187,21 @@ int eig_update_interval(eig_state_t s, int64_t k, const double *K, int64_t ldk,
                         double *lambda_out, double *V_out, int64_t ldv, int64_t m_max,
                         int64_t *m_out, void *hip_stream);
 
+/* The first-order perturbation estimate of the eigenpairs of A + K Sigma K^T
+ * (Sec. 3, eq. (11), the comparator of the paper's accuracy experiment):
+ *   lambda_j ~ lambda_j + u_j^T Sigma u_j,
+ *   v_j ~ v_j + sum_{i != j} (u_i^T Sigma u_j) / (lambda_j - lambda_i) v_i
+ * (eq. (11) as read: v_i inside the sum, this sign of the denominator, Sigma
+ * included; pairs with equal eigenvalues get no first-order term).  Writes
+ * lambda_out (n, device) and V_out (n-by-n column-major, device, leading
+ * dimension ldv) in the order of the resident eigenvalues; nothing is
+ * committed.  Only valid for a perturbation small against the eigenvalue gaps.
+ * mode: 0 or EIG_HOST_INPUT.  Asynchronous; errors as eig_update_rankk
+ * (deferred ones reported by eig_query). */
+int eig_perturb_first_order(eig_state_t s, int64_t k, const double *K, int64_t ldk,
+                            const int8_t *sigma, uint32_t mode, double *lambda_out,
+                            double *V_out, int64_t ldv, void *hip_stream);
+
 /* Synchronise `hip_stream`, report any deferred error, and copy out the
  * committed decomposition: lambda_out (n values, ascending; may be NULL) and
  * Q_out (n-by-n column-major, leading dimension ldq >= n; may be NULL).

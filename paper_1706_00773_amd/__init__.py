@@ -62,7 +62,7 @@ EIG_ROOTSOLVE_GROUPED = 1
 EIG_ROOTSOLVE_PERSISTENT = 2
 
 EXPORTED = ("eig_state_create", "eig_state_upload", "eig_update_rankk", "eig_update_interval",
-            "eig_query",
+            "eig_perturb_first_order", "eig_query",
             "eig_state_destroy", "eig_status_str", "eig_debug_fetch", "eig_batch_create",
             "eig_update_batch", "eig_batch_set", "eig_batch_get", "eig_batch_destroy",
             "eig_server_create", "eig_server_add", "eig_server_submit", "eig_server_poll",
@@ -153,6 +153,8 @@ def load_library(path: str = LIB_PATH):
     lib.eig_update_rankk.argtypes = [vp, i64, vp, i64, ctypes.POINTER(ctypes.c_int8),
                                      ctypes.c_uint32, vp]
     lib.eig_query.argtypes = [vp, vp, vp, i64, i32, ctypes.POINTER(eig_info), vp]
+    lib.eig_perturb_first_order.argtypes = [vp, i64, vp, i64, ctypes.POINTER(ctypes.c_int8),
+                                            ctypes.c_uint32, vp, vp, i64, vp]
     lib.eig_update_interval.argtypes = [vp, i64, vp, i64, ctypes.POINTER(ctypes.c_int8),
                                         ctypes.c_double, ctypes.c_double, ctypes.c_uint32, vp, vp,
                                         i64, i64, ctypes.POINTER(i64), vp]
@@ -294,6 +296,24 @@ def eig_update_interval(s, K, sigma, a: float, b: float, mode: int = 0, m_max: i
         mm = int(m.value)
         return lam[:mm], (None if vo else V[:, :mm])
     raise EigError(EIG_EINVAL, "eig_update_interval")
+
+
+def eig_perturb_first_order(s, K, sigma, stream=None):
+    """First-order perturbation estimate (eq. (11)) of the pairs of A + K diag(sigma) K^T:
+    returns (lam, V) as torch tensors on the GPU, in the order of the resident pairs."""
+    import torch
+
+    n = K.shape[0]
+    k = 1 if K.ndim == 1 else K.shape[1]
+    kp, ldk, kdev, keep = _colmajor_ptr(K, n)
+    mode = 0 if kdev else EIG_HOST_INPUT
+    sig = (ctypes.c_int8 * k)(*[int(v) for v in np.asarray(sigma).ravel()[:k]])
+    lam = torch.empty(n, dtype=torch.float64, device="cuda")
+    V = torch.empty((n, n), dtype=torch.float64, device="cuda").t()
+    _check(load_library().eig_perturb_first_order(s, k, kp, ldk, sig, mode, lam.data_ptr(),
+                                                  V.data_ptr(), n, _current_stream(stream)),
+           "eig_perturb_first_order")
+    return lam, V
 
 
 def eig_query(s, lambda_out=None, Q_out=None, stream=None, want_info: bool = True):
@@ -520,6 +540,9 @@ class EigState:
 
     def interval(self, K, sigma, a, b, mode: int = 0, m_max: int = 0, stream=None):
         return eig_update_interval(self.handle, K, sigma, a, b, mode, m_max, stream)
+
+    def perturb_first_order(self, K, sigma, stream=None):
+        return eig_perturb_first_order(self.handle, K, sigma, stream)
 
     def fetch(self, what: int, count: int, dtype=np.float64, stream=None):
         return eig_debug_fetch(self.handle, what, count, dtype, stream)

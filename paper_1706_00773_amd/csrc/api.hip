@@ -422,6 +422,44 @@ int eig_update_interval(eig_state_t s, int64_t k, const double* K, int64_t ldk,
   return EIG_OK;
 }
 
+int eig_perturb_first_order(eig_state_t s, int64_t k, const double* K, int64_t ldk,
+                            const int8_t* sigma, uint32_t mode, double* lambda_out,
+                            double* V_out, int64_t ldv, void* hip_stream) {
+  if (!s || !K || !sigma || !lambda_out || !V_out || k < 1 || ldk < s->n || ldv < s->n ||
+      s->lean)
+    return EIG_EINVAL;
+  if (k > EIG_KMAX) return EIG_EUNSUPPORTED;
+  if (k > s->n) return EIG_EINVAL;
+  if (mode & ~(uint32_t)EIG_HOST_INPUT) return EIG_EUNSUPPORTED;
+  int mask = 0;
+  for (int64_t c = 0; c < k; ++c) {
+    if (sigma[c] == 1)
+      mask |= 1 << c;
+    else if (sigma[c] != -1)
+      return EIG_EINVAL;
+  }
+  if (!s->uploaded) return EIG_ESTATE;
+  DeviceGuard g(s->device);
+  if (!g.ok) return EIG_EDEVICE;
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  const size_t n = (size_t)s->n;
+  const double* Kd = K;
+  int64_t ldkd = ldk;
+  if (mode & EIG_HOST_INPUT) {
+    HIPCHK(hipMemcpy2DAsync(s->Kbuf, n * sizeof(double), K, (size_t)ldk * sizeof(double),
+                            n * sizeof(double), (size_t)k, hipMemcpyHostToDevice, st));
+    HIPCHK(hipStreamSynchronize(st));
+    Kd = s->Kbuf;
+    ldkd = (int64_t)n;
+  }
+  Work w = make_work(s, (int)k, Kd, (int)ldkd, mask, true);
+  HIPCHK(launch_qtk(w, st));
+  HIPCHK(launch_perturb_w(w, lambda_out, st));
+  HIPCHK(launch_dgemm((int)n, (int)n, (int)n, w.Q_in, (int)n, w.W, (int)n, V_out, (int)ldv,
+                      &w.st->status, st));
+  return EIG_OK;
+}
+
 int eig_query(eig_state_t s, double* lambda_out, double* Q_out, int64_t ldq,
               int32_t ptrs_on_device, eig_info* info, void* hip_stream) {
   if (!s) return EIG_EINVAL;

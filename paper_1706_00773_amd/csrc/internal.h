@@ -184,6 +184,8 @@ hipError_t launch_finalize(const Work& w, hipStream_t s);
 hipError_t launch_wbuild(const Work& w, hipStream_t s);
 hipError_t launch_group_reflect(const Work& w, hipStream_t s);
 hipError_t launch_commit(const Work& w, hipStream_t s);
+// First-order perturbation estimate (eq. (11)): lam_out and W = I + C from U.
+hipError_t launch_perturb_w(const Work& w, double* lam_out, hipStream_t s);
 // C = A * B, column-major, FP64 MFMA.  Skipped on the device when *status != 0.
 hipError_t launch_dgemm(int M, int N, int Kd, const double* A, int lda, const double* B, int ldb,
                         double* C, int ldc, const int32_t* status, hipStream_t s);

@@ -302,4 +302,61 @@ hipError_t launch_commit_group(const Work* works, int ninst, hipStream_t s) {
   return hipGetLastError();
 }
 
+
+// ---------------------------------------------------------------------------
+// First-order perturbation estimate (Sec. 3, eq. (11) as read: the sum runs
+// over v_i, denominators lambda_j - lambda_i, Sigma included):
+//   lambda_j ~ lambda_j + u_j^T Sigma u_j,
+//   W(i, j) = delta_ij + (u_i^T Sigma u_j) / (lambda_j - lambda_i)  (i != j, and
+//             lambda_i != lambda_j),  V = Q W.
+// 256 rows x 32 columns of W per block, like wbuild; the estimate keeps the
+// original order of the eigenpairs.
+// ---------------------------------------------------------------------------
+template <int K, int CB>
+__global__ __launch_bounds__(256) void perturb_w_kernel(Work w, double* lam_out) {
+  if (update_cancelled(w.st)) return;
+  const int n = w.n;
+  const int r = blockIdx.x * 256 + threadIdx.x;
+  const int p0 = blockIdx.y * CB;
+  const int pe = min(n, p0 + CB);
+  if (r >= n) return;
+  double su[K];  // Sigma u_r
+  double lr = w.lam_in[r];
+#pragma unroll
+  for (int c = 0; c < K; ++c)
+    su[c] = (((w.sig_pos_mask >> c) & 1) ? 1.0 : -1.0) * w.U[(size_t)r * K + c];
+  if (blockIdx.y == 0) {
+    double d = 0.0;
+#pragma unroll
+    for (int c = 0; c < K; ++c) d = fma(su[c], w.U[(size_t)r * K + c], d);
+    lam_out[r] = lr + d;
+  }
+  for (int p = p0; p < pe; ++p) {
+    double val;
+    const double lp = w.lam_in[p];
+    if (p == r) {
+      val = 1.0;
+    } else if (lp == lr) {
+      val = 0.0;
+    } else {
+      double num = 0.0;
+#pragma unroll
+      for (int c = 0; c < K; ++c) num = fma(su[c], w.U[(size_t)p * K + c], num);
+      val = num / (lp - lr);
+    }
+    w.W[(size_t)p * n + r] = val;
+  }
+}
+
+template <int K>
+static hipError_t perturb_launch(const Work& w, double* lam_out, hipStream_t s) {
+  dim3 grid((w.n + 255) / 256, (w.n + WB_CB - 1) / WB_CB);
+  hipLaunchKernelGGL((perturb_w_kernel<K, WB_CB>), grid, dim3(256), 0, s, w, lam_out);
+  return hipGetLastError();
+}
+
+hipError_t launch_perturb_w(const Work& w, double* lam_out, hipStream_t s) {
+  EIGUPD_SWITCH_K(w.k, perturb_launch, w, lam_out, s)
+}
+
 }  // namespace eigupd
