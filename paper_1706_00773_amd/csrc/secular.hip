@@ -142,6 +142,41 @@ __device__ __forceinline__ void sweep(const double* __restrict__ rd, const doubl
   combine_parts<SPLIT>(G);
 }
 
+// As sweep(), and also e = sum_j sum_a u_ja^2 |r_j|, the size of the terms of the
+// diagonal of S, which bounds the rounding error of the computed S.
+template <int K, int TP, int SPLIT>
+__device__ __forceinline__ void sweep_err(const double* __restrict__ rd,
+                                          const double* __restrict__ ru, int jb, int je,
+                                          double tau, double d_o, double (&S)[Sym<K>::NS],
+                                          double (&G)[Sym<K>::NS], double& e,
+                                          PoleTile<K, TP>& tile) {
+  constexpr int NS = Sym<K>::NS;
+#pragma unroll
+  for (int q = 0; q < NS; ++q) {
+    S[q] = 0.0;
+    G[q] = 0.0;
+  }
+  double acc_e[1] = {0.0};
+  sweep_poles<K, TP, SPLIT>(rd, ru, jb, je, tau, d_o, tile, [&](double r, const double (&u)[K]) {
+    double v[K];
+#pragma unroll
+    for (int c = 0; c < K; ++c) v[c] = u[c] * r;
+#pragma unroll
+    for (int a = 0; a < K; ++a) {
+      acc_e[0] += fabs(u[a] * v[a]);
+#pragma unroll
+      for (int b = a; b < K; ++b) {
+        S[Sym<K>::at(a, b)] = fma(u[a], v[b], S[Sym<K>::at(a, b)]);
+        G[Sym<K>::at(a, b)] = fma(v[a], v[b], G[Sym<K>::at(a, b)]);
+      }
+    }
+  });
+  combine_parts<SPLIT>(S);
+  combine_parts<SPLIT>(G);
+  combine_parts<SPLIT>(acc_e);
+  e = acc_e[0];
+}
+
 // ---------------------------------------------------------------------------
 // Pole counts nu(d_s) for every segment s.
 // ---------------------------------------------------------------------------
@@ -240,13 +275,18 @@ __device__ __forceinline__ void locate_body(const Work& w) {
 enum { PH_FIRST = 0, PH_SOLVE = 1, PH_DONE = 2 };
 
 // Newton steps below STAG |tau| that no longer halve have reached the rounding
-// floor of the secular sums; the iteration stops there.
+// floor of the secular sums; the iteration stops there.  Near a pole that floor
+// can lie far above STAG |tau| (the evaluation of S loses relative accuracy in
+// tau there); it is recognised directly: Newton no longer halving while the
+// smallest |eigenvalue| of S is below NOISE_C eps times the size of the terms
+// summed into its diagonal.
 constexpr double STAG = 1e-9;
+constexpr double NOISE_C = 64.0;
 
 template <int K>
 __device__ __forceinline__ void rootsolve_body(const Work& w, int bid) {
   constexpr int NS = Sym<K>::NS, WV = Cfg<K>::WV, RPB = Cfg<K>::RPB, TP = Cfg<K>::TP;
-  __shared__ double s_part[WV][2 * NS][RPB];
+  __shared__ double s_part[WV][2 * NS + 1][RPB];
   __shared__ PoleTile<K, TP> s_tile[WV];
   __shared__ double s_tau[RPB], s_do[RPB];
   __shared__ int s_any;
@@ -314,14 +354,16 @@ __device__ __forceinline__ void rootsolve_body(const Work& w, int bid) {
   __syncthreads();
 
   for (;;) {
-    double S[NS], G[NS];
-    sweep<K, TP, Cfg<K>::SPLIT>(w.rd, w.ru, jb, je, s_tau[slot], s_do[slot], S, G, s_tile[wv]);
+    double S[NS], G[NS], err;
+    sweep_err<K, TP, Cfg<K>::SPLIT>(w.rd, w.ru, jb, je, s_tau[slot], s_do[slot], S, G, err,
+                                    s_tile[wv]);
     if (lane < RPB) {
 #pragma unroll
       for (int e = 0; e < NS; ++e) {
         s_part[wv][e][slot] = S[e];
         s_part[wv][NS + e][slot] = G[e];
       }
+      s_part[wv][2 * NS][slot] = err;
     }
     __syncthreads();
     if (wv == 0) {
@@ -336,6 +378,9 @@ __device__ __forceinline__ void rootsolve_body(const Work& w, int bid) {
           S[e] = as;
           G[e] = ag;
         }
+        err = (double)K;  // the -Sigma diagonal
+#pragma unroll 4
+        for (int q = 0; q < WV; ++q) err += s_part[q][2 * NS][slot];
 #pragma unroll
         for (int c = 0; c < K; ++c)
           S[Sym<K>::at(c, c)] -= ((w.sig_pos_mask >> c) & 1) ? 1.0 : -1.0;
@@ -343,11 +388,12 @@ __device__ __forceinline__ void rootsolve_body(const Work& w, int bid) {
         double V[K][K];
         jacobi_eig<K, true>(S, V);
         int neg = 0;
-        double phi = 0.0;
+        double phi = 0.0, thmin = INFINITY;
 #pragma unroll
         for (int m = 0; m < K; ++m) {
           const double th = S[Sym<K>::at(m, m)];
           neg += (th < 0.0) ? 1 : 0;
+          thmin = fmin(thmin, fabs(th));
           double vgv = 0.0;
 #pragma unroll
           for (int p2 = 0; p2 < K; ++p2) {
@@ -401,7 +447,12 @@ __device__ __forceinline__ void rootsolve_body(const Work& w, int bid) {
         } else if (isolated && isfinite(delta)) {
           const double tn = tau + delta;
           const double ad = fabs(delta);
-          if (ad <= 4.0 * EPSU * fabs(tn) || (ad <= STAG * fabs(tn) && ad > 0.5 * fabs(dprev))) {
+          // converged: a step at the rounding level of tau; or Newton no longer
+          // halving while its step is small, or while S is singular to within the
+          // rounding error of its sums (the noise floor of the evaluation)
+          const bool stalled = ad > 0.5 * fabs(dprev);
+          if (ad <= 4.0 * EPSU * fabs(tn) || (stalled && ad <= STAG * fabs(tn)) ||
+              (stalled && thmin <= NOISE_C * EPSU * err)) {
             conv = true;
             next = fmin(fmax(tn, tlo), thi);
           } else if (tn > tlo && tn < thi && (!last_newton || ad <= 0.5 * fabs(dxold))) {
