@@ -37,7 +37,7 @@ using namespace eigupd;
 
 namespace {
 
-enum { KIND_QTK = 0, KIND_ROOT = 1, KIND_WB = 2, KIND_REFL = 3, NKIND = 4 };
+enum { KIND_QTK = 0, KIND_ROOT = 1, KIND_WB = 2, KIND_REFL = 3, KIND_SOLVE = 4, NKIND = 5 };
 constexpr int MAX_GRAPHS = 64;
 
 // Per-call device area, laid out from the shape alone (so the pointers a graph
@@ -161,7 +161,8 @@ hipError_t enqueue(eig_batch_s* b, const Plan& p, bool vo, int root_form, int ti
   const int pgrid = (root_form == EIG_ROOTSOLVE_PERSISTENT) ? 2 * b->num_cu : 0;
   for (int k = 1; k <= KMAX; ++k)
     if (p.cnt[k])
-      STEP(launch_rootsolve_group(k, group(k, KIND_ROOT), p.blocks[k][KIND_ROOT], pgrid,
+      STEP(launch_rootsolve_group(k, group(k, KIND_SOLVE), p.blocks[k][KIND_SOLVE],
+                                  group(k, KIND_ROOT), p.blocks[k][KIND_ROOT], pgrid,
                                   b->d_queue + k, st));
   if (ev) STEP(hipEventRecord(ev[1], st));
   for (int k = 1; k <= KMAX; ++k)
@@ -363,7 +364,8 @@ int eig_update_batch(eig_batch_t b, const eig_batch_item* items, int32_t count, 
     const int k = (int)it.k, n = (int)s->n;
     hw[pos] = make_work(s, k, it.K, (int)it.ldk, masks[p.order[pos]], vo);
     const int local = pos - p.off[k];
-    const int nb[NKIND] = {qtk_blocks(n, k), root_blocks(n), wbuild_blocks(n), reflect_blocks(n)};
+    const int nb[NKIND] = {qtk_blocks(n, k), root_blocks(n), wbuild_blocks(n), reflect_blocks(n),
+                           solve_blocks(n)};
     for (int kind = 0; kind < NKIND; ++kind) {
       int* pre = hp + p.poff[k][kind];
       pre[local] = run[k][kind];

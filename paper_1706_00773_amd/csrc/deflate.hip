@@ -286,6 +286,7 @@ __device__ __forceinline__ void deflate_body(const Work& w) {
     info->r_hi = n_d;
     info->e_lo = 0;
     info->e_hi = cd;
+    info->root_next = 0;
   }
 }
 

@@ -56,6 +56,8 @@ struct DevInfo {    // written by the kernels of one update
   int32_t loc_alpha;   // 1: the pole counts came from the residue signs
   int32_t r_lo, r_hi;  // roots of the reduced problem to solve (all: 0, n_d)
   int32_t e_lo, e_hi;  // deflated eigenvalues to keep (all: 0, n_defl)
+  int32_t root_next;   // root solver: roots handed out so far (from r_lo)
+  int32_t pad_;
 };
 
 struct ColParam {   // one output column of W
@@ -192,7 +194,8 @@ hipError_t launch_dgemm(int M, int N, int Kd, const double* A, int lda, const do
 // Grouped launches over `ninst` instances of one rank k (blocks = total blocks,
 // Group.prefix built from the per-instance counts below).
 int qtk_blocks(int n, int k);
-int root_blocks(int n);
+int root_blocks(int n);   // polecount / rootvec blocks of an instance
+int solve_blocks(int n);  // rootsolve blocks of an instance
 int wbuild_blocks(int n);
 int reflect_blocks(int n);
 int gemm_tiles(int n, int bt);
@@ -202,8 +205,9 @@ hipError_t launch_polecount_group(int k, const Group& g, int blocks, hipStream_t
 hipError_t launch_locate_group(const Work* works, int ninst, hipStream_t s);
 // persistent_grid > 0: that many blocks draw (instance, root block) items from
 // *queue (reset on the stream first); 0: one block per item.
-hipError_t launch_rootsolve_group(int k, const Group& g, int blocks, int persistent_grid,
-                                  int* queue, hipStream_t s);
+hipError_t launch_rootsolve_group(int k, const Group& gs, int solve_blocks, const Group& gv,
+                                  int vec_blocks, int persistent_grid, int* queue,
+                                  hipStream_t s);
 hipError_t launch_finalize_group(int k, const Work* works, int ninst, hipStream_t s);
 hipError_t launch_wbuild_group(int k, const Group& g, int blocks, hipStream_t s);
 hipError_t launch_reflect_group(int k, const Group& g, int blocks, hipStream_t s);

@@ -142,35 +142,82 @@ __device__ __forceinline__ void sweep(const double* __restrict__ rd, const doubl
   combine_parts<SPLIT>(G);
 }
 
-// As sweep(), and also e = sum_j sum_a u_ja^2 |r_j|, the size of the terms of the
-// diagonal of S, which bounds the rounding error of the computed S.
+// Pole value written into the unused tail of a tile: with u = 0 it contributes
+// nothing, and tau - (PAD_D - d_o) is never 0.
+constexpr double PAD_D = 1e300;
+
+// As sweep(), and also e = sum_j sum_a |u_ja v_ja| = sum_j ||u_j||^2 |r_j|, the size
+// of the terms summed into the diagonal of S, which bounds its rounding error.
+// For the root solver only: x is strictly between two poles, so 1/(x - d_j) needs
+// no guard, and the pole loop is the same for every lane (the tile tail is padded
+// with zero-weight poles), which lets the compiler pipeline the LDS reads.
 template <int K, int TP, int SPLIT>
 __device__ __forceinline__ void sweep_err(const double* __restrict__ rd,
                                           const double* __restrict__ ru, int jb, int je,
                                           double tau, double d_o, double (&S)[Sym<K>::NS],
                                           double (&G)[Sym<K>::NS], double& e,
                                           PoleTile<K, TP>& tile) {
+  static_assert(TP % SPLIT == 0, "a padded tile holds whole rounds");
   constexpr int NS = Sym<K>::NS;
+  constexpr int PER = TP / 64;
+  const int lane = threadIdx.x & 63;
+  const int part = lane / (64 / SPLIT);
 #pragma unroll
   for (int q = 0; q < NS; ++q) {
     S[q] = 0.0;
     G[q] = 0.0;
   }
   double acc_e[1] = {0.0};
-  sweep_poles<K, TP, SPLIT>(rd, ru, jb, je, tau, d_o, tile, [&](double r, const double (&u)[K]) {
-    double v[K];
+  double pd[PER], pu[PER][K];
+  auto load = [&](int base) {
 #pragma unroll
-    for (int c = 0; c < K; ++c) v[c] = u[c] * r;
+    for (int p = 0; p < PER; ++p) {
+      const int j = base + p * 64 + lane;
+      const bool ok = j < je;
+      pd[p] = ok ? rd[j] : PAD_D;
 #pragma unroll
-    for (int a = 0; a < K; ++a) {
-      acc_e[0] += fabs(u[a] * v[a]);
+      for (int c = 0; c < K; ++c) pu[p][c] = ok ? ru[(size_t)j * K + c] : 0.0;
+    }
+  };
+  if (jb < je) load(jb);
+  for (int base = jb; base < je; base += TP) {
 #pragma unroll
-      for (int b = a; b < K; ++b) {
-        S[Sym<K>::at(a, b)] = fma(u[a], v[b], S[Sym<K>::at(a, b)]);
-        G[Sym<K>::at(a, b)] = fma(v[a], v[b], G[Sym<K>::at(a, b)]);
+    for (int p = 0; p < PER; ++p) {
+      tile.d[p * 64 + lane] = pd[p];
+#pragma unroll
+      for (int c = 0; c < K; ++c) tile.u[p * 64 + lane][c] = pu[p][c];
+    }
+    wave_sync();
+    if (base + TP < je) load(base + TP);
+    const int rounds = (min(TP, je - base) + SPLIT - 1) / SPLIT;
+#pragma unroll 4
+    for (int q0 = 0; q0 < rounds; ++q0) {
+      const int q = q0 * SPLIT + part;
+      double u[K], v[K];
+#pragma unroll
+      for (int c = 0; c < K; ++c) u[c] = tile.u[q][c];
+      double r = __builtin_amdgcn_rcp(tau - (tile.d[q] - d_o));
+      {
+        const double y = tau - (tile.d[q] - d_o);
+        double t = fma(-y, r, 1.0);
+        r = fma(r, t, r);
+        t = fma(-y, r, 1.0);
+        r = fma(r, t, r);
+      }
+#pragma unroll
+      for (int c = 0; c < K; ++c) v[c] = u[c] * r;
+#pragma unroll
+      for (int a = 0; a < K; ++a) {
+        acc_e[0] = fma(fabs(u[a]), fabs(v[a]), acc_e[0]);
+#pragma unroll
+        for (int b = a; b < K; ++b) {
+          S[Sym<K>::at(a, b)] = fma(u[a], v[b], S[Sym<K>::at(a, b)]);
+          G[Sym<K>::at(a, b)] = fma(v[a], v[b], G[Sym<K>::at(a, b)]);
+        }
       }
     }
-  });
+    wave_sync();
+  }
   combine_parts<SPLIT>(S);
   combine_parts<SPLIT>(G);
   combine_parts<SPLIT>(acc_e);
@@ -283,104 +330,150 @@ enum { PH_FIRST = 0, PH_SOLVE = 1, PH_DONE = 2 };
 constexpr double STAG = 1e-9;
 constexpr double NOISE_C = 64.0;
 
+// Launch shape of the root solver: RPB root slots per block, each slot's pole
+// sums split over WV waves x SPLIT parts of a wave.  A slot whose root has
+// converged takes the next unsolved root of the update (a counter in DevInfo),
+// so a block runs until the update's roots run out rather than until the
+// slowest of a fixed set of roots has converged.
 template <int K>
-__device__ __forceinline__ void rootsolve_body(const Work& w, int bid) {
-  constexpr int NS = Sym<K>::NS, WV = Cfg<K>::WV, RPB = Cfg<K>::RPB, TP = Cfg<K>::TP;
+struct RsCfg {
+  static constexpr int WV = Cfg<K>::WV;
+  static constexpr int RPB = 8;
+  static constexpr int SPLIT = 64 / RPB;
+  static constexpr int TP = Cfg<K>::TP;
+};
+
+// The state of the root held by one solver slot.  It lives in LDS between
+// evaluations, so that the pole sweep, which every wave runs, keeps only its own
+// accumulators in registers.
+struct SlotState {
+  double a, b, ra, rb;          // interval ends (pole values) and their multiplicities
+  double tlo, thi, tau, d_o;    // bracket and iterate, offsets from the origin pole d_o
+  double dxold, dprev;          // previous step sizes
+  int i, phase, t, clo, chi;    // root, stage, interval, counts at the bracket ends
+  int evals, rows_below, o_seg;
+  int two_sided, last_newton;
+  int it_min, it_max;           // statistics over the roots this slot has solved
+  long long it_sum;
+};
+
+template <int K>
+__device__ __forceinline__ void rootsolve_body(const Work& w) {
+  constexpr int NS = Sym<K>::NS, WV = RsCfg<K>::WV, RPB = RsCfg<K>::RPB, TP = RsCfg<K>::TP;
+  constexpr int SPLIT = RsCfg<K>::SPLIT;
   __shared__ double s_part[WV][2 * NS + 1][RPB];
   __shared__ PoleTile<K, TP> s_tile[WV];
+  __shared__ SlotState s_st[RPB];
   __shared__ double s_tau[RPB], s_do[RPB];
   __shared__ int s_any;
   if (update_cancelled(w.st)) return;
   const int n_d = w.info->n_d, n_s = w.info->n_s;
   const int r_lo = w.info->r_lo, r_hi = w.info->r_hi;  // the roots to solve
-  const int i0 = r_lo + bid * RPB;
-  if (i0 >= r_hi) return;
+  if (r_lo >= r_hi) return;
   const int lane = threadIdx.x & 63, slot = lane % RPB;
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int chunk = (n_d + WV - 1) / WV;
   const int jb = min(n_d, wv * chunk), je = min(n_d, jb + chunk);
+  const bool owner = (wv == 0) && (lane < RPB);  // lane `slot` of wave 0 steers slot `slot`
 
-  // solver state, meaningful in lanes 0..RPB-1 of wave 0
-  const int i = i0 + slot;
-  const bool owner = (wv == 0) && (lane < RPB);
-  const bool valid = owner && (i < r_hi);
-  const int tgt = i + 1;
-  int phase = valid ? PH_FIRST : PH_DONE;
-  int t = 0, clo = 0, chi = 0, evals = 0, rows_below = 0;
-  double a = 0.0, b = 0.0, ra = 0.0, rb = 0.0, tlo = 0.0, thi = 0.0, tau = 0.0;
-  double dxold = 0.0, dprev = INFINITY, d_o = 0.0;
-  int o_seg = 0;
-  bool two_sided = false, last_newton = false;
-  if (valid) {
-    t = min(max(w.root_t[i], 0), n_s);
-    clo = w.root_clo[i];
-    chi = w.root_chi[i];
-    rows_below = w.seg_start[t];  // rows strictly below any x inside interval t
+  // takes the next root of the update into the slot (or retires the slot)
+  auto start = [&](SlotState& z) {
+    z.i = r_lo + atomicAdd(&w.info->root_next, 1);
+    if (z.i >= r_hi) {
+      z.phase = PH_DONE;
+      return;
+    }
+    z.phase = PH_FIRST;
+    z.evals = 0;
+    z.dprev = INFINITY;
+    z.last_newton = 0;
+    z.a = z.b = z.ra = z.rb = 0.0;
+    const int t = min(max(w.root_t[z.i], 0), n_s);
+    z.t = t;
+    z.clo = w.root_clo[z.i];
+    z.chi = w.root_chi[z.i];
+    z.rows_below = w.seg_start[t];  // rows strictly below any x inside interval t
     const bool has_a = t > 0, has_b = t < n_s;
-    two_sided = has_a && has_b;
+    z.two_sided = has_a && has_b;
     if (has_a) {
-      a = w.rd[w.seg_start[t - 1]];
-      ra = (double)w.seg_r[t - 1];
+      z.a = w.rd[w.seg_start[t - 1]];
+      z.ra = (double)w.seg_r[t - 1];
     }
     if (has_b) {
-      b = w.rd[w.seg_start[t]];
-      rb = (double)w.seg_r[t];
+      z.b = w.rd[w.seg_start[t]];
+      z.rb = (double)w.seg_r[t];
     }
-    if (two_sided) {
-      o_seg = t - 1;
-      d_o = a;
-      tlo = 0.0;
-      thi = b - a;
-      tau = 0.5 * thi;
+    if (z.two_sided) {
+      z.o_seg = t - 1;
+      z.d_o = z.a;
+      z.tlo = 0.0;
+      z.thi = z.b - z.a;
+      z.tau = 0.5 * z.thi;
     } else if (has_a) {  // right of the last pole
-      o_seg = t - 1;
-      d_o = a;
-      tlo = 0.0;
-      thi = w.info->upper - a;
-      tau = 0.5 * thi;
+      z.o_seg = t - 1;
+      z.d_o = z.a;
+      z.tlo = 0.0;
+      z.thi = w.info->upper - z.a;
+      z.tau = 0.5 * z.thi;
     } else {  // left of the first pole
-      o_seg = t;
-      d_o = b;
-      tlo = w.info->lower - b;
-      thi = 0.0;
-      tau = 0.5 * tlo;
+      z.o_seg = t;
+      z.d_o = z.b;
+      z.tlo = w.info->lower - z.b;
+      z.thi = 0.0;
+      z.tau = 0.5 * z.tlo;
     }
-    dxold = thi - tlo;
-  }
+    z.dxold = z.thi - z.tlo;
+  };
   if (owner) {
-    s_tau[slot] = tau;
-    s_do[slot] = d_o;
+    SlotState z;
+    z.it_min = 0x7fffffff;
+    z.it_max = 0;
+    z.it_sum = 0;
+    z.tau = z.d_o = 0.0;
+    start(z);
+    s_st[slot] = z;
+    s_tau[slot] = z.tau;
+    s_do[slot] = z.d_o;
+  }
+  if (wv == 0) {
+    const unsigned long long live = __ballot(owner && s_st[slot].phase != PH_DONE);
+    if (lane == 0) s_any = (live != 0ull);
   }
   __syncthreads();
+  if (!s_any) return;
 
   for (;;) {
-    double S[NS], G[NS], err;
-    sweep_err<K, TP, Cfg<K>::SPLIT>(w.rd, w.ru, jb, je, s_tau[slot], s_do[slot], S, G, err,
-                                    s_tile[wv]);
-    if (lane < RPB) {
+    {
+      double S[NS], G[NS], err;
+      sweep_err<K, TP, SPLIT>(w.rd, w.ru, jb, je, s_tau[slot], s_do[slot], S, G, err,
+                              s_tile[wv]);
+      if (lane < RPB) {
 #pragma unroll
-      for (int e = 0; e < NS; ++e) {
-        s_part[wv][e][slot] = S[e];
-        s_part[wv][NS + e][slot] = G[e];
+        for (int e = 0; e < NS; ++e) {
+          s_part[wv][e][slot] = S[e];
+          s_part[wv][NS + e][slot] = G[e];
+        }
+        s_part[wv][2 * NS][slot] = err;
       }
-      s_part[wv][2 * NS][slot] = err;
     }
     __syncthreads();
     if (wv == 0) {
-      if (phase != PH_DONE) {
+      bool live = false;
+      if (owner && s_st[slot].phase != PH_DONE) {
+        SlotState z = s_st[slot];
+        double S[NS], G[NS];
+        double err = (double)K;  // the -Sigma diagonal
 #pragma unroll
-        for (int e = 0; e < NS; ++e) {
-          double as = 0.0, ag = 0.0;
-          for (int q = 0; q < WV; ++q) {
-            as += s_part[q][e][slot];
-            ag += s_part[q][NS + e][slot];
+        for (int e = 0; e < NS; ++e) S[e] = G[e] = 0.0;
+#pragma unroll 1
+        for (int q = 0; q < WV; ++q) {
+#pragma unroll
+          for (int e = 0; e < NS; ++e) {
+            S[e] += s_part[q][e][slot];
+            G[e] += s_part[q][NS + e][slot];
           }
-          S[e] = as;
-          G[e] = ag;
+          err += s_part[q][2 * NS][slot];
         }
-        err = (double)K;  // the -Sigma diagonal
-#pragma unroll 4
-        for (int q = 0; q < WV; ++q) err += s_part[q][2 * NS][slot];
 #pragma unroll
         for (int c = 0; c < K; ++c)
           S[Sym<K>::at(c, c)] -= ((w.sig_pos_mask >> c) & 1) ? 1.0 : -1.0;
@@ -404,98 +497,103 @@ __device__ __forceinline__ void rootsolve_body(const Work& w, int bid) {
           }
           phi -= vgv / th;
         }
-        ++evals;
-        const int cnt = rows_below + neg - w.info->p;
+        ++z.evals;
+        const int tgt = z.i + 1;
+        const int cnt = z.rows_below + neg - w.info->p;
         // d log g / dx = ra/(x-a) + rb/(x-b) + tr(S^{-1} S'); the Newton step is -1/that
         double da, db;
-        if (o_seg == t - 1) {
-          da = tau;
-          db = tau - (b - a);
+        if (z.o_seg == z.t - 1) {
+          da = z.tau;
+          db = z.tau - (z.b - z.a);
         } else {
-          da = tau + (b - a);
-          db = tau;
+          da = z.tau + (z.b - z.a);
+          db = z.tau;
         }
-        if (ra > 0.0) phi += ra / da;
-        if (rb > 0.0) phi += rb / db;
+        if (z.ra > 0.0) phi += z.ra / da;
+        if (z.rb > 0.0) phi += z.rb / db;
         const double delta = -1.0 / phi;
-        if (phase == PH_FIRST) {
-          phase = PH_SOLVE;
-          if (two_sided && cnt < tgt) {
+        if (z.phase == PH_FIRST) {
+          z.phase = PH_SOLVE;
+          if (z.two_sided && cnt < tgt) {
             // the root lies in the right half: move the origin to b
-            o_seg = t;
-            d_o = b;
-            const double gap = b - a;
-            tau -= gap;
-            tlo -= gap;
-            thi = 0.0;
+            z.o_seg = z.t;
+            z.d_o = z.b;
+            const double gap = z.b - z.a;
+            z.tau -= gap;
+            z.tlo -= gap;
+            z.thi = 0.0;
           }
         }
         if (cnt >= tgt) {
-          thi = tau;
-          chi = cnt;
+          z.thi = z.tau;
+          z.chi = cnt;
         } else {
-          tlo = tau;
-          clo = cnt;
+          z.tlo = z.tau;
+          z.clo = cnt;
         }
-        const double width = thi - tlo;
-        const double mid = tlo + 0.5 * width;
-        const bool isolated = (clo == tgt - 1) && (chi == tgt);
+        const double width = z.thi - z.tlo;
+        const double mid = z.tlo + 0.5 * width;
+        const bool isolated = (z.clo == tgt - 1) && (z.chi == tgt);
         double next = mid;
         bool conv = false;
-        if (width <= 4.0 * EPSU * fmax(fabs(tlo), fabs(thi))) {
+        if (width <= 4.0 * EPSU * fmax(fabs(z.tlo), fabs(z.thi))) {
           conv = true;
         } else if (isolated && isfinite(delta)) {
-          const double tn = tau + delta;
+          const double tn = z.tau + delta;
           const double ad = fabs(delta);
           // converged: a step at the rounding level of tau; or Newton no longer
           // halving while its step is small, or while S is singular to within the
           // rounding error of its sums (the noise floor of the evaluation)
-          const bool stalled = ad > 0.5 * fabs(dprev);
+          const bool stalled = ad > 0.5 * fabs(z.dprev);
           if (ad <= 4.0 * EPSU * fabs(tn) || (stalled && ad <= STAG * fabs(tn)) ||
               (stalled && thmin <= NOISE_C * EPSU * err)) {
             conv = true;
-            next = fmin(fmax(tn, tlo), thi);
-          } else if (tn > tlo && tn < thi && (!last_newton || ad <= 0.5 * fabs(dxold))) {
+            next = fmin(fmax(tn, z.tlo), z.thi);
+          } else if (tn > z.tlo && tn < z.thi && (!z.last_newton || ad <= 0.5 * fabs(z.dxold))) {
             // an in-bracket Newton step is taken unless the previous step was one
             // too and this one does not halve it
-            dxold = delta;
+            z.dxold = delta;
             next = tn;
           } else {
-            dxold = 0.5 * width;
+            z.dxold = 0.5 * width;
           }
-          dprev = delta;
+          z.dprev = delta;
         }
-        last_newton = !conv && (next != mid);
-        if (!conv && evals >= MAX_EVALS) {
+        z.last_newton = !conv && (next != mid);
+        if (!conv && z.evals >= MAX_EVALS) {
           conv = true;
           atomicOr(&w.st->status, ST_NOCONV);
         }
-        if (!conv && !(next > tlo && next < thi)) next = mid;
-        if (next == 0.0) next = (tlo == 0.0) ? thi : tlo;
-        tau = next;
+        if (!conv && !(next > z.tlo && next < z.thi)) next = mid;
+        if (next == 0.0) next = (z.tlo == 0.0) ? z.thi : z.tlo;
+        z.tau = next;
         if (conv) {
-          phase = PH_DONE;
-          w.root_o[i] = o_seg;
-          w.root_tau[i] = tau;
-          w.root_clo[i] = clo;
-          w.root_chi[i] = chi;
-          w.root_it[i] = evals;
+          w.root_o[z.i] = z.o_seg;
+          w.root_tau[z.i] = z.tau;
+          w.root_clo[z.i] = z.clo;
+          w.root_chi[z.i] = z.chi;
+          w.root_it[z.i] = z.evals;
+          z.it_min = min(z.it_min, z.evals);
+          z.it_max = max(z.it_max, z.evals);
+          z.it_sum += z.evals;
+          start(z);
         }
+        s_st[slot] = z;
+        s_tau[slot] = z.tau;
+        s_do[slot] = z.d_o;
+        live = z.phase != PH_DONE;
       }
-      if (owner) {
-        s_tau[slot] = tau;
-        s_do[slot] = d_o;
-      }
-      const unsigned long long live = __ballot(phase != PH_DONE);
-      if (lane == 0) s_any = (live != 0ull);
+      const unsigned long long any = __ballot(live);
+      if (lane == 0) s_any = (any != 0ull);
     }
     __syncthreads();
     if (!s_any) break;
   }
-  if (valid) {
-    atomicMin(&w.info->it_min, evals);
-    atomicMax(&w.info->it_max, evals);
-    atomicAdd((unsigned long long*)&w.info->it_sum, (unsigned long long)evals);
+  if (owner && s_st[slot].it_max > 0) {
+    const SlotState& z = s_st[slot];
+    atomicMin(&w.info->it_min, z.it_min);
+    atomicMax(&w.info->it_max, z.it_max);
+    atomicAdd((unsigned long long*)&w.info->it_sum, (unsigned long long)z.it_sum);
   }
 }
 
@@ -1034,20 +1132,19 @@ __global__ __launch_bounds__(LNT) void locate_group(const Work* __restrict__ wor
 }
 
 template <int K>
-__global__ __launch_bounds__(64 * Cfg<K>::WV) void rootsolve_kernel(Work w) {
-  rootsolve_body<K>(w, blockIdx.x);
+__global__ __launch_bounds__(64 * RsCfg<K>::WV) void rootsolve_kernel(Work w) {
+  rootsolve_body<K>(w);
 }
 template <int K>
-__global__ __launch_bounds__(64 * Cfg<K>::WV) void rootsolve_group(Group g) {
-  const int i = group_instance(g, blockIdx.x);
-  rootsolve_body<K>(g.works[i], blockIdx.x - g.prefix[i]);
+__global__ __launch_bounds__(64 * RsCfg<K>::WV) void rootsolve_group(Group g) {
+  rootsolve_body<K>(g.works[group_instance(g, blockIdx.x)]);
 }
 // A fixed grid of blocks; each takes the next item of the queue (an atomic
 // counter that starts at 0) until all `total` items are taken.  Every block
 // leaves the loop once the counter has passed `total`.
 template <int K>
-__global__ __launch_bounds__(64 * Cfg<K>::WV) void rootsolve_persist(Group g, int total,
-                                                                      int* queue) {
+__global__ __launch_bounds__(64 * RsCfg<K>::WV) void rootsolve_persist(Group g, int total,
+                                                                        int* queue) {
   __shared__ int s_item;
   for (;;) {
     __syncthreads();
@@ -1055,8 +1152,7 @@ __global__ __launch_bounds__(64 * Cfg<K>::WV) void rootsolve_persist(Group g, in
     __syncthreads();
     const int item = s_item;
     if (item >= total) break;
-    const int i = group_instance(g, item);
-    rootsolve_body<K>(g.works[i], item - g.prefix[i]);
+    rootsolve_body<K>(g.works[group_instance(g, item)]);
   }
 }
 
@@ -1071,6 +1167,9 @@ __global__ __launch_bounds__(64 * Cfg<K>::WV) void rootvec_group(Group g) {
 }
 
 int root_blocks(int n) { return (n + 31) / 32; }
+// Two roots per slot on average: enough blocks for two per CU at n = 8192, few
+// enough that a slot's refills balance the roots' differing iteration counts.
+int solve_blocks(int n) { return (n + 2 * 8 - 1) / (2 * 8); }
 
 template <int K>
 static hipError_t polecount_group_launch(const Group& g, int blocks, hipStream_t s) {
@@ -1080,21 +1179,23 @@ static hipError_t polecount_group_launch(const Group& g, int blocks, hipStream_t
 }
 
 template <int K>
-static hipError_t rootsolve_group_launch(const Group& g, int blocks, int persistent_grid,
-                                         int* queue, hipStream_t s) {
+static hipError_t rootsolve_group_launch(const Group& gs, int solve_blocks, const Group& gv,
+                                         int vec_blocks, int persistent_grid, int* queue,
+                                         hipStream_t s) {
   hipError_t e;
   if (persistent_grid > 0) {
     hipLaunchKernelGGL(zero_ints_kernel, dim3(1), dim3(64), 0, s, queue, 1);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((rootsolve_persist<K>), dim3(min(persistent_grid, blocks)),
-                       dim3(64 * Cfg<K>::WV), 0, s, g, blocks, queue);
+    hipLaunchKernelGGL((rootsolve_persist<K>), dim3(min(persistent_grid, solve_blocks)),
+                       dim3(64 * RsCfg<K>::WV), 0, s, gs, solve_blocks, queue);
   } else {
-    hipLaunchKernelGGL((rootsolve_group<K>), dim3(blocks), dim3(64 * Cfg<K>::WV), 0, s, g);
+    hipLaunchKernelGGL((rootsolve_group<K>), dim3(solve_blocks), dim3(64 * RsCfg<K>::WV), 0, s,
+                       gs);
   }
   e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((rootvec_group<K>), dim3(blocks), dim3(64 * Cfg<K>::WV), 0, s, g);
+  hipLaunchKernelGGL((rootvec_group<K>), dim3(vec_blocks), dim3(64 * Cfg<K>::WV), 0, s, gv);
   return hipGetLastError();
 }
 
@@ -1109,10 +1210,12 @@ hipError_t launch_locate_group(const Work* works, int ninst, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_rootsolve_group(int k, const Group& g, int blocks, int persistent_grid,
-                                  int* queue, hipStream_t s) {
-  if (blocks <= 0) return hipSuccess;
-  EIGUPD_SWITCH_K(k, rootsolve_group_launch, g, blocks, persistent_grid, queue, s)
+hipError_t launch_rootsolve_group(int k, const Group& gs, int solve_blocks, const Group& gv,
+                                  int vec_blocks, int persistent_grid, int* queue,
+                                  hipStream_t s) {
+  if (solve_blocks <= 0) return hipSuccess;
+  EIGUPD_SWITCH_K(k, rootsolve_group_launch, gs, solve_blocks, gv, vec_blocks, persistent_grid,
+                  queue, s)
 }
 
 template <int K>
@@ -1125,10 +1228,12 @@ static hipError_t polecount_launch(const Work& w, hipStream_t s) {
 template <int K>
 static hipError_t rootsolve_launch(const Work& w, int nroots, hipStream_t s) {
   if (nroots <= 0) return hipSuccess;
-  const int grid = (nroots + Cfg<K>::RPB - 1) / Cfg<K>::RPB;
-  hipLaunchKernelGGL((rootsolve_kernel<K>), dim3(grid), dim3(64 * Cfg<K>::WV), 0, s, w);
+  static_assert(RsCfg<K>::RPB == 8, "solve_blocks assumes 8 slots per block");
+  hipLaunchKernelGGL((rootsolve_kernel<K>), dim3(solve_blocks(nroots)), dim3(64 * RsCfg<K>::WV),
+                     0, s, w);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
+  const int grid = (nroots + Cfg<K>::RPB - 1) / Cfg<K>::RPB;
   hipLaunchKernelGGL((rootvec_kernel<K>), dim3(grid), dim3(64 * Cfg<K>::WV), 0, s, w);
   return hipGetLastError();
 }
