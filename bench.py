@@ -413,6 +413,77 @@ def interval_report(args, dev):
             "modes": out}
 
 
+def sturm_chain_report(args, dev):
+    """The secular Sturm chain counter (eig_sturm_chain, Sec. 2.2, eqs. (4)-(9)):
+    synchronous time per call at 64 count points, the members it builds before its
+    first non-positive c, and -- with the lowest eigenvalues divided out first
+    (eq. (9)) -- a complete chain; beside it the inertia counter's cost (the first
+    phase of eig_update_interval on an empty interval) and the oracle's chain on
+    the host at n = 200."""
+    import torch
+
+    import oracle
+    import paper_1706_00773_amd as eu
+    from oracle import sturm_chain as sc
+    from paper_1706_00773_amd import workloads as wl
+
+    def timed(fn, reps=5):
+        ts = []
+        r = None
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            r = fn()
+            torch.cuda.synchronize()
+            ts.append(1000.0 * (time.perf_counter() - t0))
+        return float(np.median(ts)), r
+
+    rows = []
+    for n, k in ((200, 3), (1024, 3), (8192, 2), (8192, 3)):
+        u = wl.random_small(n, k, seed=n + k) if n <= 1024 else \
+            (wl.plain_rank2(n, seed=1000, device=str(dev), min_gap=1e-12) if k == 2
+             else wl.general_rankk(k, n=n, device=str(dev)))
+        Qd = u.Q if isinstance(u.Q, torch.Tensor) else \
+            torch.from_numpy(np.asfortranarray(u.Q)).to(dev).t().contiguous().t()
+        state = eu.EigState(n, 0)
+        state.upload(torch.from_numpy(np.asarray(u.lam)).to(dev), Qd)
+        Kd = torch.from_numpy(np.asfortranarray(u.K)).to(dev).t().contiguous().t()
+        lo, hi = float(np.min(u.lam)) - 1.0, float(np.max(u.lam)) + 1.0
+        x = torch.linspace(lo, hi, 64, dtype=torch.float64, device=dev)
+        ms, (_, _, info) = timed(lambda: state.sturm_chain(Kd, u.sigma, x))
+        row = {"n": n, "k": k, "ms": round(ms, 3), "levels": int(info.levels),
+               "complete": bool(info.complete), "lower_bound": int(info.lower_bound)}
+        mid = float(np.median(u.lam))
+        ms_in, _ = timed(lambda: state.interval(Kd, u.sigma, mid, mid, mode=eu.EIG_VALUES_ONLY))
+        row["inertia_count_ms"] = round(ms_in, 3)
+        if n <= 1024:
+            # divide out all but the top 20 eigenvalues: the remaining chain completes
+            A = (Qd * torch.from_numpy(np.asarray(u.lam)).to(dev)) @ Qd.T + \
+                (Kd * torch.tensor(u.sigma, dtype=torch.float64, device=dev)) @ Kd.T
+            ev = torch.linalg.eigvalsh((A + A.T) / 2)
+            xi = ev[: n - 20].contiguous()
+            ms_d, (cnt, _, info_d) = timed(lambda: state.sturm_chain(Kd, u.sigma, x, xi=xi))
+            ref = torch.searchsorted(ev.contiguous(), x.contiguous())
+            row["found_zeros"] = {"divided_out": n - 20, "ms": round(ms_d, 3),
+                                  "levels": int(info_d.levels), "complete": bool(info_d.complete),
+                                  "counts_equal_eigvalsh": bool(torch.equal(cnt, ref))}
+        state.close()
+        rows.append(row)
+    # the oracle's chain on the host, n = 200, k = 3
+    u = wl.random_small(200, 3, seed=203)
+    U = oracle.qtk(u.Q, u.K)
+    t0 = time.perf_counter()
+    a = np.array([oracle.alpha(u.lam, U, u.sigma, i) for i in range(200)])
+    ch = sc.build(u.lam, a)
+    xs = np.linspace(u.lam.min() - 1, u.lam.max() + 1, 64)
+    _ = [sc.count_below(ch, v) for v in xs]
+    cpu_ms = 1000.0 * (time.perf_counter() - t0)
+    return {"workload": "secular Sturm chain counter (eig_sturm_chain), 64 count points, "
+                        "random updates with distinct poles; synchronous calls, median of 5",
+            "rows": rows,
+            "oracle_host_n200_k3_ms": round(cpu_ms, 1), "oracle_levels_n200_k3": ch.levels}
+
+
 def perturbation_sweep(args, dev):
     """The accuracy experiment of the paper's Sec. 3 (Fig. 6, 7) on synthetic data: N = 100,
     norm(K) in {0.01, 0.3}, rank k = 1..8, perturbation K K^T (all signs +1).  For the
@@ -533,6 +604,8 @@ def main():
                     help="report subsets of the spectrum (eig_update_interval)")
     ap.add_argument("--perturbation-sweep", action="store_true",
                     help="the N = 100 accuracy experiment against eq. (11)")
+    ap.add_argument("--sturm-chain", action="store_true",
+                    help="report the secular Sturm chain counter")
     ap.add_argument("--serve", action="store_true", help="report the serving loop")
     ap.add_argument("--serve-matrices", type=int, default=64)
     ap.add_argument("--serve-requests", type=int, default=4096)
@@ -577,6 +650,9 @@ def main():
         return
     if args.perturbation_sweep:
         print(json.dumps(perturbation_sweep(args, dev)), flush=True)
+        return
+    if args.sturm_chain:
+        print(json.dumps(sturm_chain_report(args, dev)), flush=True)
         return
     n, k = args.n, args.k
     log = lambda *a: print(*a, file=sys.stderr, flush=True)

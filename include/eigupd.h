@@ -202,6 +202,49 @@ int eig_perturb_first_order(eig_state_t s, int64_t k, const double *K, int64_t l
                             const int8_t *sigma, uint32_t mode, double *lambda_out,
                             double *V_out, int64_t ldv, void *hip_stream);
 
+/* The secular Sturm chain of the update A' = A + K Sigma K^T (Sec. 2.2,
+ * eqs. (4)-(9)) as an eigenvalue counter, without changing the state.
+ * The reduced secular function f_0(x) = 1 - sum_j alpha_j / (x - d_j) (its
+ * residues alpha_j are eq. (2)) gives the polynomial p_0 = f_0 prod (x - d_j);
+ * each member p_m of its Sturm sequence is kept in secular form (c_m and
+ * N - m residues; the division step with the B_m of the long division taken
+ * with its sign corrected).  The build stops at the first c_m that is not
+ * positive, as the section prescribes: the chain is then partial and only a
+ * lower bound on the number of zeros.  Known eigenvalues xi (e.g. found
+ * earlier) are divided out first by eq. (9), each removing one of the lowest
+ * poles, which leaves a shorter chain.
+ *   k, K, ldk, sigma   as for eig_update_rankk (K a device pointer)
+ *   xi, n_xi           device pointer: n_xi known eigenvalues of the reduced
+ *                      problem (none of them a pole), strictly ascending; may
+ *                      be NULL when n_xi == 0
+ *   x, n_x             device pointer: the points to count at
+ *   counts             device pointer, n_x entries: eigenvalues of A' below
+ *                      x[i] (the chain's count, plus the known and the deflated
+ *                      eigenvalues below x[i]); -1 where x[i] is a pole of the
+ *                      chain.  Exact only when info->complete is 1.
+ *   c_out, c_max       device pointer (may be NULL when c_max == 0): the first
+ *                      min(c_max, info->levels) leading constants c_m
+ *   info               host pointer: the chain's size and state
+ * The reduced problem must have simple poles (no two kept rows at one
+ * eigenvalue after deflation); otherwise EIG_EUNSUPPORTED.  The members are
+ * held in the state's eigenvector work buffer (about N^2 / 2 doubles).
+ * Synchronous.  Errors: EIG_EINVAL (arguments, n_xi > N, xi not ascending or
+ * on a pole), EIG_EUNSUPPORTED, EIG_ESTATE, EIG_ENOMEM, EIG_EDEVICE, and a
+ * device error (a non-finite input) returned directly and cleared. */
+typedef struct eig_chain_info {
+  int64_t n_poles;     /* N: poles of the chain (the reduced problem's, less n_xi) */
+  int64_t levels;      /* members p_0 .. p_{levels-1} built */
+  int64_t lower_bound; /* zeros the leading positive c's guarantee: their number - 1 */
+  int64_t n_deflated;  /* eigenvalues deflated before the chain (tiny rows, groups) */
+  int32_t complete;    /* 1: all N + 1 members, every c_m > 0: the counts are exact */
+  int32_t reserved;
+} eig_chain_info;
+
+int eig_sturm_chain(eig_state_t s, int64_t k, const double *K, int64_t ldk,
+                    const int8_t *sigma, const double *xi, int64_t n_xi, const double *x,
+                    int64_t n_x, int64_t *counts, double *c_out, int64_t c_max,
+                    eig_chain_info *info, void *hip_stream);
+
 /* Synchronise `hip_stream`, report any deferred error, and copy out the
  * committed decomposition: lambda_out (n values, ascending; may be NULL) and
  * Q_out (n-by-n column-major, leading dimension ldq >= n; may be NULL).

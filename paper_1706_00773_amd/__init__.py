@@ -62,7 +62,7 @@ EIG_ROOTSOLVE_GROUPED = 1
 EIG_ROOTSOLVE_PERSISTENT = 2
 
 EXPORTED = ("eig_state_create", "eig_state_upload", "eig_update_rankk", "eig_update_interval",
-            "eig_perturb_first_order", "eig_query",
+            "eig_perturb_first_order", "eig_sturm_chain", "eig_query",
             "eig_state_destroy", "eig_status_str", "eig_debug_fetch", "eig_batch_create",
             "eig_update_batch", "eig_batch_set", "eig_batch_get", "eig_batch_destroy",
             "eig_server_create", "eig_server_add", "eig_server_submit", "eig_server_poll",
@@ -92,6 +92,12 @@ class eig_info(ctypes.Structure):
     def as_dict(self):
         return {f: (list(getattr(self, f)) if f == "ms" else getattr(self, f))
                 for f, _ in self._fields_}
+
+
+class eig_chain_info(ctypes.Structure):
+    _fields_ = [("n_poles", ctypes.c_int64), ("levels", ctypes.c_int64),
+                ("lower_bound", ctypes.c_int64), ("n_deflated", ctypes.c_int64),
+                ("complete", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class eig_batch_item(ctypes.Structure):
@@ -158,6 +164,8 @@ def load_library(path: str = LIB_PATH):
     lib.eig_update_interval.argtypes = [vp, i64, vp, i64, ctypes.POINTER(ctypes.c_int8),
                                         ctypes.c_double, ctypes.c_double, ctypes.c_uint32, vp, vp,
                                         i64, i64, ctypes.POINTER(i64), vp]
+    lib.eig_sturm_chain.argtypes = [vp, i64, vp, i64, ctypes.POINTER(ctypes.c_int8), vp, i64, vp,
+                                    i64, vp, vp, i64, ctypes.POINTER(eig_chain_info), vp]
     lib.eig_state_destroy.argtypes = [vp]
     lib.eig_status_str.argtypes = [ctypes.c_int]
     lib.eig_status_str.restype = ctypes.c_char_p
@@ -314,6 +322,36 @@ def eig_perturb_first_order(s, K, sigma, stream=None):
                                                   V.data_ptr(), n, _current_stream(stream)),
            "eig_perturb_first_order")
     return lam, V
+
+
+def eig_sturm_chain(s, K, sigma, x=None, xi=None, c_max: int = 0, stream=None):
+    """Secular Sturm chain counter (Sec. 2.2, eqs. (4)-(9)) of A + K diag(sigma) K^T,
+    without changing the state.  K: n-by-k torch tensor on the GPU; x: points (torch
+    float64 on the GPU) to count the eigenvalues below; xi: known eigenvalues of the
+    reduced problem, ascending, divided out first (eq. (9)).  Returns (counts as an
+    int64 torch tensor or None, the first c_max leading constants or None, eig_chain_info)."""
+    import torch
+
+    n = K.shape[0]
+    k = 1 if K.ndim == 1 else K.shape[1]
+    kp, ldk, kdev, keep = _colmajor_ptr(K, n)
+    if not kdev:
+        raise ValueError("K must be a device tensor")
+    sig = (ctypes.c_int8 * k)(*[int(v) for v in np.asarray(sigma).ravel()[:k]])
+    xs = None if x is None else x.to(dtype=torch.float64).contiguous()
+    xis = None if xi is None else xi.to(dtype=torch.float64).contiguous()
+    n_x = 0 if xs is None else xs.numel()
+    n_xi = 0 if xis is None else xis.numel()
+    counts = torch.empty(max(n_x, 1), dtype=torch.int64, device="cuda")
+    cbuf = torch.empty(max(int(c_max), 1), dtype=torch.float64, device="cuda")
+    info = eig_chain_info()
+    _check(load_library().eig_sturm_chain(
+        s, k, kp, ldk, sig, None if xis is None else xis.data_ptr(), n_xi,
+        None if xs is None else xs.data_ptr(), n_x, counts.data_ptr() if n_x else None,
+        cbuf.data_ptr() if c_max > 0 else None, int(c_max), ctypes.byref(info),
+        _current_stream(stream)), "eig_sturm_chain")
+    c = cbuf[: min(int(c_max), int(info.levels))] if c_max > 0 else None
+    return (counts[:n_x] if n_x else None), c, info
 
 
 def eig_query(s, lambda_out=None, Q_out=None, stream=None, want_info: bool = True):
@@ -540,6 +578,9 @@ class EigState:
 
     def interval(self, K, sigma, a, b, mode: int = 0, m_max: int = 0, stream=None):
         return eig_update_interval(self.handle, K, sigma, a, b, mode, m_max, stream)
+
+    def sturm_chain(self, K, sigma, x=None, xi=None, c_max: int = 0, stream=None):
+        return eig_sturm_chain(self.handle, K, sigma, x, xi, c_max, stream)
 
     def perturb_first_order(self, K, sigma, stream=None):
         return eig_perturb_first_order(self.handle, K, sigma, stream)

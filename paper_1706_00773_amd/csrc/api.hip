@@ -422,6 +422,88 @@ int eig_update_interval(eig_state_t s, int64_t k, const double* K, int64_t ldk,
   return EIG_OK;
 }
 
+int eig_sturm_chain(eig_state_t s, int64_t k, const double* K, int64_t ldk,
+                    const int8_t* sigma, const double* xi, int64_t n_xi, const double* x,
+                    int64_t n_x, int64_t* counts, double* c_out, int64_t c_max,
+                    eig_chain_info* info, void* hip_stream) {
+  if (!s || !K || !sigma || !info || k < 1 || ldk < s->n || s->lean) return EIG_EINVAL;
+  if (n_xi < 0 || (n_xi > 0 && !xi) || n_x < 0 || (n_x > 0 && (!x || !counts)) || c_max < 0 ||
+      (c_max > 0 && !c_out) || n_x > INT32_MAX)
+    return EIG_EINVAL;
+  if (k > EIG_KMAX) return EIG_EUNSUPPORTED;
+  if (k > s->n) return EIG_EINVAL;
+  int mask = 0;
+  for (int64_t c = 0; c < k; ++c) {
+    if (sigma[c] == 1)
+      mask |= 1 << c;
+    else if (sigma[c] != -1)
+      return EIG_EINVAL;
+  }
+  if (!s->uploaded) return EIG_ESTATE;
+  DeviceGuard g(s->device);
+  if (!g.ok) return EIG_EDEVICE;
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  const size_t n = (size_t)s->n;
+  Work w = make_work(s, (int)k, K, (int)ldk, mask, true);
+  // U, deflation (the chain needs the reduced problem's simple poles)
+  HIPCHK(launch_qtk(w, st));
+  HIPCHK(launch_deflate(w, st));
+  HIPCHK(hipStreamSynchronize(st));
+  DevState ds;
+  DevInfo di;
+  HIPCHK(hipMemcpy(&ds, s->w.st, sizeof(ds), hipMemcpyDeviceToHost));
+  HIPCHK(hipMemcpy(&di, s->w.info, sizeof(di), hipMemcpyDeviceToHost));
+  if (ds.status != 0) {
+    // report a device error and clear it: the state keeps its committed pair
+    DevState z = ds;
+    z.status = 0;
+    if (hipMemcpy(s->w.st, &z, sizeof(z), hipMemcpyHostToDevice) != hipSuccess) return EIG_EDEVICE;
+    return status_from_bits(ds.status);
+  }
+  if (di.n_s != di.n_d) return EIG_EUNSUPPORTED;
+  if (n_xi > di.n_d) return EIG_EINVAL;
+  const int n_d = di.n_d, N = n_d - (int)n_xi;
+  // the members live in W when it is large enough, else in a temporary buffer
+  const size_t need = chain_ws_doubles(n_d);
+  double* ws = w.W;
+  double* tmp = nullptr;
+  if (need > n * n) {
+    if (hipMalloc(&tmp, need * sizeof(double)) != hipSuccess) {
+      (void)hipGetLastError();
+      return EIG_ENOMEM;
+    }
+    ws = tmp;
+  }
+  struct Free {
+    double* p;
+    ~Free() {
+      if (p) (void)hipFree(p);
+    }
+  } free_tmp{tmp};
+  HIPCHK(launch_chain(w, n_d, xi, (int)n_xi, ws, &w.info->alpha_bad, st));
+  HIPCHK(hipStreamSynchronize(st));
+  int out[2];
+  int bad = 0;
+  HIPCHK(hipMemcpy(out, ws + 3 * (size_t)n_d + 1, sizeof(out), hipMemcpyDeviceToHost));
+  HIPCHK(hipMemcpy(&bad, &w.info->alpha_bad, sizeof(int), hipMemcpyDeviceToHost));
+  if (bad) return EIG_EINVAL;
+  const int levels = out[0];
+  HIPCHK(launch_chain_count(w, n_d, xi, (int)n_xi, ws, levels, x, (int)n_x, counts, st));
+  if (c_max > 0)
+    HIPCHK(hipMemcpyAsync(c_out, ws + 2 * (size_t)n_d,
+                          (size_t)std::min<int64_t>(c_max, levels) * sizeof(double),
+                          hipMemcpyDeviceToDevice, st));
+  HIPCHK(hipStreamSynchronize(st));
+  info->n_poles = N;
+  info->levels = levels;
+  info->complete = out[1];
+  info->lower_bound = out[1] ? N : (int64_t)levels - 2;
+  info->n_deflated = (int64_t)n - n_d;
+  info->reserved = 0;
+  s->last_k = (int)k;
+  return EIG_OK;
+}
+
 int eig_perturb_first_order(eig_state_t s, int64_t k, const double* K, int64_t ldk,
                             const int8_t* sigma, uint32_t mode, double* lambda_out,
                             double* V_out, int64_t ldv, void* hip_stream) {

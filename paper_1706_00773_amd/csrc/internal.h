@@ -205,6 +205,14 @@ hipError_t launch_polecount_group(int k, const Group& g, int blocks, hipStream_t
 hipError_t launch_locate_group(const Work* works, int ninst, hipStream_t s);
 // persistent_grid > 0: that many blocks draw (instance, root block) items from
 // *queue (reset on the stream first); 0: one block per item.
+// Secular Sturm chain (chain.hip): residues, found-zero deflation, level 1 and
+// the serial build into ws (chain_ws_doubles(n_d) doubles); then the counts.
+size_t chain_ws_doubles(int n_d);
+hipError_t launch_chain(const Work& w, int n_d, const double* xi, int n_xi, double* ws, int* bad,
+                        hipStream_t s);
+hipError_t launch_chain_count(const Work& w, int n_d, const double* xi, int n_xi,
+                              const double* ws, int levels, const double* x, int n_x,
+                              int64_t* counts, hipStream_t s);
 hipError_t launch_rootsolve_group(int k, const Group& gs, int solve_blocks, const Group& gv,
                                   int vec_blocks, int persistent_grid, int* queue,
                                   hipStream_t s);

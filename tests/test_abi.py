@@ -63,7 +63,7 @@ def _c_layout(struct, fields):
 
 
 @pytest.mark.parametrize("cls", ["eig_info", "eig_batch_item", "eig_completion",
-                                 "eig_server_info"])
+                                 "eig_server_info", "eig_chain_info"])
 def test_struct_layouts_match_the_header(cls):
     st = getattr(eu, cls)
     names = [f for f, _ in st._fields_]
@@ -89,6 +89,9 @@ def test_null_state_is_rejected():
     assert lib.eig_state_destroy(None) == eu.EIG_EINVAL
     assert lib.eig_state_upload(None, None, None, 1, 0, None) == eu.EIG_EINVAL
     assert lib.eig_debug_fetch(None, 1, None, 0, None) == eu.EIG_EINVAL
+    info = eu.eig_chain_info()
+    assert lib.eig_sturm_chain(None, 2, K.ctypes.data, 4, sig, None, 0, None, 0, None, None, 0,
+                               ctypes.byref(info), None) == eu.EIG_EINVAL
 
 
 def test_no_device_reports_edevice():
