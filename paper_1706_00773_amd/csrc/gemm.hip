@@ -7,9 +7,10 @@
 //
 // Tiling: 128x128 block tile, 16-deep k slices, 256 threads = 4 waves in a 2x2
 // arrangement, each wave a 64x64 sub-tile = 4x4 MFMA tiles (64 doubles of
-// accumulator per lane).  Slices are staged global -> registers -> LDS with
-// double buffering: the next slice's global loads are in flight while the MFMAs
-// consume the current one, one barrier per slice.  Block ids are remapped so
+// accumulator per lane).  Slices are staged global -> registers -> LDS with two
+// register sets and two LDS buffers: while the MFMAs consume slice s from LDS,
+// slice s + 1 waits in registers to be stored and the global loads of slice
+// s + 2 are in flight (two slices of latency hidden), one barrier per slice.  Block ids are remapped so
 // that the blocks resident on one XCD (blocks are dealt round-robin to the 8
 // XCDs) cover one compact group of 8 tile rows, sharing its A panel and the B
 // panels in that XCD's L2.  LDS rows are padded to 144 doubles (288 dwords, an
@@ -63,9 +64,9 @@ __device__ __forceinline__ void dgemm_tile(int M, int N, int Kd, const double* _
   const int a_k = tid >> 4, a_m = (tid & 15) * 2;
   const int b_n = tid / TPC, b_k = (tid % TPC) * KPT;  // B: column n0+b_n, rows k0+b_k ..
   const bool full_m = vec && (m0 + BT <= M), full_n = vec && (n0 + BT <= N);
-  double ra[2 * AQ], rb[KPT];
+  double ra0[2 * AQ], rb0[KPT], ra1[2 * AQ], rb1[KPT];
 
-  auto gload = [&](int k0) {
+  auto gload = [&](int k0, double (&ra)[2 * AQ], double (&rb)[KPT]) {
     const bool full_k = (k0 + GBK <= Kd);
     const int ka = k0 + a_k;
     if (full_m && full_k) {
@@ -99,7 +100,7 @@ __device__ __forceinline__ void dgemm_tile(int M, int N, int Kd, const double* _
       }
     }
   };
-  auto sstore = [&](int buf) {
+  auto sstore = [&](int buf, const double (&ra)[2 * AQ], const double (&rb)[KPT]) {
 #pragma unroll
     for (int q = 0; q < AQ; ++q)
       *reinterpret_cast<double2*>(&As[buf][a_k][a_m + 32 * q]) = double2{ra[2 * q], ra[2 * q + 1]};
@@ -114,13 +115,8 @@ __device__ __forceinline__ void dgemm_tile(int M, int N, int Kd, const double* _
     for (int j = 0; j < FT; ++j) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
 
   const int nk = (Kd + GBK - 1) / GBK;
-  gload(0);
-  sstore(0);
-  __syncthreads();
   const int fr = lane & 15, fk = lane >> 4;
-  for (int kt = 0; kt < nk; ++kt) {
-    const int cur = kt & 1;
-    if (kt + 1 < nk) gload((kt + 1) * GBK);
+  auto compute = [&](int cur) {
 #pragma unroll
     for (int ks = 0; ks < GBK / 4; ++ks) {
       const int kr = ks * 4 + fk;
@@ -135,9 +131,24 @@ __device__ __forceinline__ void dgemm_tile(int M, int N, int Kd, const double* _
         for (int j = 0; j < FT; ++j)
           acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
     }
-    if (kt + 1 < nk) sstore(cur ^ 1);
+  };
+  gload(0, ra0, rb0);
+  sstore(0, ra0, rb0);
+  if (nk > 1) gload(GBK, ra1, rb1);
+  __syncthreads();
+  // slice s sits in register set s & 1 until it is stored; two slices in flight
+  int kt = 0;
+  for (; kt + 1 < nk; kt += 2) {
+    if (kt + 2 < nk) gload((kt + 2) * GBK, ra0, rb0);
+    compute(0);
+    sstore(1, ra1, rb1);
+    __syncthreads();
+    if (kt + 3 < nk) gload((kt + 3) * GBK, ra1, rb1);
+    compute(1);
+    if (kt + 2 < nk) sstore(0, ra0, rb0);
     __syncthreads();
   }
+  if (kt < nk) compute(0);
   // epilogue: lane holds rows l/16 + 4v of column l%16 of each 16x16 tile; for a
   // fixed v the wave writes 4 consecutive rows of 16 columns
 #pragma unroll
