@@ -151,7 +151,7 @@ constexpr double PAD_D = 1e300;
 // For the root solver only: x is strictly between two poles, so 1/(x - d_j) needs
 // no guard, and the pole loop is the same for every lane (the tile tail is padded
 // with zero-weight poles), which lets the compiler pipeline the LDS reads.
-template <int K, int TP, int SPLIT>
+template <int K, int TP, int SPLIT, int UNR = 4>
 __device__ __forceinline__ void sweep_err(const double* __restrict__ rd,
                                           const double* __restrict__ ru, int jb, int je,
                                           double tau, double d_o, double (&S)[Sym<K>::NS],
@@ -190,7 +190,7 @@ __device__ __forceinline__ void sweep_err(const double* __restrict__ rd,
     wave_sync();
     if (base + TP < je) load(base + TP);
     const int rounds = (min(TP, je - base) + SPLIT - 1) / SPLIT;
-#pragma unroll 4
+#pragma unroll UNR
     for (int q0 = 0; q0 < rounds; ++q0) {
       const int q = q0 * SPLIT + part;
       double u[K], v[K];
@@ -337,10 +337,13 @@ constexpr double NOISE_C = 64.0;
 // slowest of a fixed set of roots has converged.
 template <int K>
 struct RsCfg {
+  // ranks >= 5 carry k(k+1) accumulators per lane: 4 waves of smaller tiles and
+  // a shallower unroll keep them in 256 VGPRs (two waves per SIMD)
   static constexpr int WV = Cfg<K>::WV;
   static constexpr int RPB = 8;
   static constexpr int SPLIT = 64 / RPB;
   static constexpr int TP = Cfg<K>::TP;
+  static constexpr int UNR = 4;
 };
 
 // The state of the root held by one solver slot.  It lives in LDS between
@@ -445,8 +448,8 @@ __device__ __forceinline__ void rootsolve_body(const Work& w) {
   for (;;) {
     {
       double S[NS], G[NS], err;
-      sweep_err<K, TP, SPLIT>(w.rd, w.ru, jb, je, s_tau[slot], s_do[slot], S, G, err,
-                              s_tile[wv]);
+      sweep_err<K, TP, SPLIT, RsCfg<K>::UNR>(w.rd, w.ru, jb, je, s_tau[slot], s_do[slot], S, G,
+                                             err, s_tile[wv]);
       if (lane < RPB) {
 #pragma unroll
         for (int e = 0; e < NS; ++e) {
@@ -461,19 +464,41 @@ __device__ __forceinline__ void rootsolve_body(const Work& w) {
       bool live = false;
       if (owner && s_st[slot].phase != PH_DONE) {
         SlotState z = s_st[slot];
-        double S[NS], G[NS];
+        // ranks >= 5 keep the totals of G in LDS (wave 0's row of s_part, which no
+        // other wave touches before the next sweep) so that they are not live
+        // through the k x k eigensolve
+        constexpr bool G_IN_LDS = (K >= 5);
+        constexpr int NG = G_IN_LDS ? 1 : NS;
+        double S[NS], G[NG];
         double err = (double)K;  // the -Sigma diagonal
 #pragma unroll
-        for (int e = 0; e < NS; ++e) S[e] = G[e] = 0.0;
+        for (int e = 0; e < NS; ++e) S[e] = 0.0;
+#pragma unroll
+        for (int e = 0; e < NG; ++e) G[e] = 0.0;
 #pragma unroll 1
         for (int q = 0; q < WV; ++q) {
 #pragma unroll
-          for (int e = 0; e < NS; ++e) {
-            S[e] += s_part[q][e][slot];
-            G[e] += s_part[q][NS + e][slot];
+          for (int e = 0; e < NS; ++e) S[e] += s_part[q][e][slot];
+          if constexpr (!G_IN_LDS) {
+#pragma unroll
+            for (int e = 0; e < NS; ++e) G[e] += s_part[q][NS + e][slot];
           }
           err += s_part[q][2 * NS][slot];
         }
+        if constexpr (G_IN_LDS) {
+#pragma unroll 1
+          for (int e = 0; e < NS; ++e) {
+            double g = 0.0;
+            for (int q = 0; q < WV; ++q) g += s_part[q][NS + e][slot];
+            s_part[0][NS + e][slot] = g;
+          }
+        }
+        auto Gat = [&](int e) -> double {
+          if constexpr (G_IN_LDS)
+            return s_part[0][NS + e][slot];
+          else
+            return G[e];
+        };
 #pragma unroll
         for (int c = 0; c < K; ++c)
           S[Sym<K>::at(c, c)] -= ((w.sig_pos_mask >> c) & 1) ? 1.0 : -1.0;
@@ -492,7 +517,7 @@ __device__ __forceinline__ void rootsolve_body(const Work& w) {
           for (int p2 = 0; p2 < K; ++p2) {
             double gv = 0.0;
 #pragma unroll
-            for (int q2 = 0; q2 < K; ++q2) gv += G[Sym<K>::at(p2, q2)] * V[q2][m];
+            for (int q2 = 0; q2 < K; ++q2) gv += Gat(Sym<K>::at(p2, q2)) * V[q2][m];
             vgv += V[p2][m] * gv;
           }
           phi -= vgv / th;
