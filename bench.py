@@ -31,6 +31,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "rank-k eigen-updates/sec vs full GPU re-eigh at equal accuracy; p50/p99 latency"
 PEAK_FP64_MFMA_TFLOPS = 78.6
+PEAK_FP64_VALU_TFLOPS = 78.6
 PEAK_HBM_GBS = 8000.0
 
 
@@ -735,6 +736,21 @@ def main():
     phase_ms = {nm: round(float(phases[:, i].mean()), 4) for i, nm in enumerate(names)}
     qtk_gbs = (8.0 * n * n + 16.0 * n * k) / (phase_ms["qtk"] * 1e-3) / 1e9 if phase_ms["qtk"] else 0
 
+    # whole update against the sum of its steps' ideal times: U = Q^T K and W at
+    # HBM speed, the root work (pole counts, Newton evaluations, null vectors:
+    # 6 + k + k(k+1) flop per pole and count or vector sweep, 6 + k + 2k(k+1) per
+    # Newton evaluation) at the FP64 vector peak, Q W at the FP64 MFMA peak
+    n_d = n - int(info.n_deflated_rows)
+    root_flop = float(n_d) ** 2 * (3 * (6 + k + k * (k + 1)) + info.iters_mean * (6 + k + 2 * k * (k + 1)))
+    ideal = {"qtk": (8.0 * n * n + 16.0 * n * k) / (PEAK_HBM_GBS * 1e9) * 1e3,
+             "roots": root_flop / (PEAK_FP64_VALU_TFLOPS * 1e12) * 1e3,
+             "wbuild": 8.0 * n * n / (PEAK_HBM_GBS * 1e9) * 1e3,
+             "dgemm": 2.0 * n ** 3 / (PEAK_FP64_MFMA_TFLOPS * 1e12) * 1e3}
+    ideal_ms = sum(ideal.values())
+    whole = {"ideal_ms": round(ideal_ms, 3), "measured_ms": round(ms_per_step, 3),
+             "frac": round(ideal_ms / ms_per_step, 4),
+             "ideal_steps_ms": {kk: round(v, 4) for kk, v in ideal.items()}}
+
     # sanity: the final state is orthonormal on a sample of columns
     lam_now = torch.empty(n, dtype=torch.float64, device=dev)
     Q_now = torch.empty((n, n), dtype=torch.float64, device=dev).t()
@@ -770,6 +786,7 @@ def main():
                      if args.locate_residues else "inertia pole counts"),
         "orth_sample_max": orth,
         "roofline": roofline,
+        "roofline_whole_update": whole,
     }
 
     if not args.no_reeigh:
