@@ -130,6 +130,28 @@ def test_tiny_rows_deflate():
     _check_full(u2, lo, Qo, ref_lam, ref_Q)
 
 
+@pytest.mark.parametrize("k", [2, 3, 4])
+def test_weakly_coupled_rows(k):
+    """Rows of U with norms 1e-3 .. 1e-11, all above the deflation threshold: their
+    roots lie within about ||u_j||^2 of their poles, where the evaluation of S
+    loses relative accuracy in tau (the noise-floor stop of the root solver)."""
+    print(f"case weakly coupled rows k={k}", flush=True)
+    n = 400
+    u = wl.random_small(n, k, seed=90 + k)
+    Qn = np.asarray(u.Q)
+    U = Qn.T @ u.K
+    rng = np.random.default_rng(5 + k)
+    rows = rng.choice(n, 50, replace=False)
+    norms = 10.0 ** -rng.uniform(3.0, 11.0, rows.size)
+    U[rows] *= (norms / np.linalg.norm(U[rows], axis=1))[:, None]
+    K = np.asfortranarray(Qn @ U)
+    lo, Qo, info, _ = run_update(u.lam, Qn, K, u.sigma)
+    assert info.n_deflated_rows == 0
+    ref_lam, ref_Q, _ = oracle.update(u.lam, Qn, K, u.sigma)
+    _check_full(wl.Update(u.lam, Qn, K, u.sigma), lo, Qo, ref_lam, ref_Q)
+    assert info.iters_max < 160
+
+
 def test_equal_poles_group_deflation():
     """Groups of exactly equal poles: the m - k extra rows of each group deflate."""
     n, k = 200, 2
