@@ -19,16 +19,38 @@ struct Sym {
 // One plane rotation that annihilates a(p,q) (two-sided, symmetric Schur
 // decomposition of the 2x2 block, Golub & Van Loan Sec. 8.5), applied to the
 // packed matrix and, if VEC, to the columns of V.
+// 1/x and 1/sqrt(x) from the hardware estimates refined by two Newton steps
+// (to about one ulp): the rotation needs c^2 + s^2 = 1 to working precision,
+// not correctly rounded quotients.
+__device__ __forceinline__ double nr_recip(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-x, r, 1.0);
+  return fma(r, e, r);
+}
+__device__ __forceinline__ double nr_rsqrt(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  const double hx = 0.5 * x;
+  double e = fma(-hx * y, y, 0.5);
+  y = fma(y, e, y);
+  e = fma(-hx * y, y, 0.5);
+  return fma(y, e, y);
+}
+
 template <int N, int P, int Qc, bool VEC>
 __device__ __forceinline__ void jacobi_rotate(double (&a)[Sym<N>::NS], double (&V)[N][N]) {
   constexpr int ipq = Sym<N>::at(P, Qc), ipp = Sym<N>::at(P, P), iqq = Sym<N>::at(Qc, Qc);
   const double apq = a[ipq];
   const bool z = (apq == 0.0);
-  const double theta = z ? 0.0 : (a[iqq] - a[ipp]) / (2.0 * apq);
+  const double theta = z ? 0.0 : (a[iqq] - a[ipp]) * nr_recip(2.0 * apq);
   const double at = fabs(theta);
-  double t = (at > 1e150) ? 0.5 / theta : copysign(1.0, theta) / (at + sqrt(theta * theta + 1.0));
-  t = z ? 0.0 : t;
-  const double c = 1.0 / sqrt(t * t + 1.0);
+  // t = sign(theta) / (|theta| + sqrt(theta^2 + 1)); for huge theta, 1 / (2 theta)
+  const double h = fma(theta, theta, 1.0);
+  double t = (at > 1e150) ? 0.5 * nr_recip(theta)
+                          : copysign(1.0, theta) * nr_recip(at + h * nr_rsqrt(h));
+  t = (z || !(at == at)) ? 0.0 : t;
+  const double c = nr_rsqrt(fma(t, t, 1.0));
   const double s = t * c;
   a[ipp] -= t * apq;
   a[iqq] += t * apq;

@@ -103,17 +103,24 @@ def test_complete_chain_matches_the_oracle(n, k):
 
 @pytest.mark.parametrize("k", [2, 3])
 def test_partial_chain_stops_like_the_oracle(k):
+    """Where the chain is well determined (the oracle's c_m moves by less than 10%
+    under 2-eps perturbations of the residues and is positive) the GPU's c_m must
+    agree and stay positive; past that point the member at which rounding first
+    makes a c non-positive is itself rounding-determined, on both sides."""
     print(f"case sturm chain partial n=300 k={k}", flush=True)
     u = wl.random_small(300, k, seed=7 + k)
     ch, ev, _, d, al = _oracle_chain(u)
     assert not ch.complete
     _, c, info = _run(u, c_max=400)
     assert info.complete == 0 and info.n_poles == 300
-    assert abs(info.levels - ch.levels) <= 3
     assert info.lower_bound == info.levels - 2
     assert np.all(c[: info.levels - 1] > 0) and not c[info.levels - 1] > 0
-    # the members before the breakdown region
-    _check_c(c, ch, d, al, min(info.levels, ch.levels) - 4)
+    L = max(ch.levels, info.levels)
+    spread = _sensitivity(d, al, L)
+    ref = sc.build(d, al, stop_nonpositive=False)
+    m_rel = next((m for m in range(L) if spread[m] >= 0.1 or not ref.c[m] > 0), L)
+    assert info.levels - 1 >= m_rel, (info.levels, m_rel)
+    _check_c(c, ch, d, al, min(m_rel, ch.levels, info.levels))
 
 
 @pytest.mark.parametrize("n,s,k", [(60, 36, 3), (200, 180, 2)])
