@@ -57,7 +57,8 @@ def make_perturbations(n, k, count, seed, dev):
 
 
 def cpu_baseline(lam, Qn, K, sig, roots_sample, cols_sample, seed=7):
-    """Time the oracle on a bounded sample of one update and scale to a whole update."""
+    """Time the oracle on one whole update (default), or on a sample of its roots and
+    columns scaled to a whole update."""
     import oracle
 
     n = lam.size
@@ -85,7 +86,11 @@ def cpu_baseline(lam, Qn, K, sig, roots_sample, cols_sample, seed=7):
         "unit": "updates/s",
         "cores": oracle.get_threads(),
         "kind": "oracle",
-        "sample": (f"one n={n} k={K.shape[1]} update: U = Q^T K in full ({t_u:.2f} s), "
+        "sample": (f"one whole n={n} k={K.shape[1]} update: U = Q^T K ({t_u:.2f} s), all {n} "
+                   f"roots by count bisection ({t_r:.2f} s), their eigenvectors ({t_v:.2f} s), "
+                   f"Q W ({t_g:.2f} s); {total:.1f} s"
+                   if (m == n and c == n) else
+                   f"one n={n} k={K.shape[1]} update: U = Q^T K in full ({t_u:.2f} s), "
                    f"{m} of {n} roots by count bisection ({t_r:.2f} s) and their eigenvectors "
                    f"({t_v:.2f} s) scaled by n/{m}, Q W on {c} columns ({t_g:.2f} s) scaled "
                    f"by n/{c}; estimated {total:.1f} s per update"),
@@ -586,8 +591,10 @@ def main():
     ap.add_argument("--k", type=int, default=2)
     ap.add_argument("--no-reeigh", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--cpu-roots", type=int, default=2048)
-    ap.add_argument("--cpu-cols", type=int, default=1024)
+    ap.add_argument("--cpu-roots", type=int, default=1 << 30,
+                    help="roots the CPU oracle solves (default: all)")
+    ap.add_argument("--cpu-cols", type=int, default=1 << 30,
+                    help="columns of Q W the CPU oracle forms (default: all)")
     ap.add_argument("--save-input", metavar="NPZ",
                     help="only generate the resident decomposition and write it to NPZ")
     ap.add_argument("--load-input", metavar="NPZ",
@@ -819,7 +826,7 @@ def main():
         del A
 
     if not args.no_cpu:
-        log("[bench] CPU oracle baseline on a bounded sample")
+        log("[bench] CPU oracle baseline (the whole update unless --cpu-roots/--cpu-cols bound it)")
         Qn = Q0.cpu().numpy()  # column-major view -> Fortran-ordered array
         Qn = np.asfortranarray(Qn)
         K0 = np.asfortranarray(perts[0][0].cpu().numpy())
