@@ -102,3 +102,16 @@ def test_no_device_reports_edevice():
     lib = eu.load_library()
     h = ctypes.c_void_p()
     assert lib.eig_state_create(ctypes.byref(h), 16, 0) == eu.EIG_EDEVICE
+
+
+def test_c_client_compiles(tmp_path):
+    """The plain C client (tests/c_client/eigupd_client.c) builds against the header
+    and the library with gcc alone, no Python or torch types involved."""
+    import importlib.util
+
+    spec = importlib.util.spec_from_file_location(
+        "c_client_build", os.path.join(ROOT, "tests", "c_client", "build.py"))
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    out = mod.build(str(tmp_path / "client"))
+    assert os.path.exists(out)
