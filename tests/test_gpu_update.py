@@ -152,6 +152,33 @@ def test_weakly_coupled_rows(k):
     assert info.iters_max < 160
 
 
+@pytest.mark.parametrize("e", [-300, 300])
+@pytest.mark.parametrize("k", [2, 5])
+def test_scale_invariance(e, k):
+    """A' scaled by 2^e (lambda by 2^e, K by 2^(e/2)): powers of two scale exactly,
+    so the update must return 2^e times the eigenvalues of the unscaled problem and
+    the same eigenvectors, to the FP64 bar, with nothing overflowing or
+    underflowing in the secular sums (u^2 ~ 2^e, 1/(x - d) ~ 2^-e, S' terms
+    ~ 2^-e) -- and agree with the oracle on the scaled problem."""
+    print(f"case scale 2^{e} k={k}", flush=True)
+    n = 300
+    u = wl.random_small(n, k, seed=700 + k, knorm=1.5)
+    lam1, Q1, info1, _ = run_update(u.lam, u.Q, u.K, u.sigma)
+    f = 2.0 ** e
+    lam_s = u.lam * f
+    K_s = np.asfortranarray(u.K * 2.0 ** (e // 2))
+    lo, Qo, info, _ = run_update(lam_s, u.Q, K_s, u.sigma)
+    assert info.n_deflated_rows == info1.n_deflated_rows
+    scale = np.abs(lo).max()
+    assert np.abs(lo - lam1 * f).max() <= EVAL_TOL * scale
+    ref_lam, ref_Q, _ = oracle.update(lam_s, np.asarray(u.Q), K_s, u.sigma)
+    _check_full(wl.Update(lam_s, u.Q, K_s, u.sigma), lo, Qo, ref_lam, ref_Q)
+    cols = isolated_columns(lam1, 1e-6, np.abs(lam1).max())
+    if cols.size:
+        Qa = align_signs(Qo[:, cols], Q1[:, cols])
+        assert np.abs(Qa - Q1[:, cols]).max() <= VEC_TOL
+
+
 def test_equal_poles_group_deflation():
     """Groups of exactly equal poles: the m - k extra rows of each group deflate."""
     n, k = 200, 2
