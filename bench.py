@@ -624,8 +624,8 @@ def main():
                     help="only run a plain 1 GiB device copy (for HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on exactly one GPU (asked for --gpus {args.gpus}); the update "
-              "is single-GPU in this build", file=sys.stderr)
+        print(f"bench.py runs on exactly one GPU (asked for --gpus {args.gpus}): the library "
+              "implements the single-GPU update only", file=sys.stderr)
         sys.exit(2)
 
     import torch

@@ -75,11 +75,11 @@ def _close(insts):
         b.close()
 
 
-def _run_rounds(batch, insts, shapes, rounds, seed, check_oracle=False, between=None):
+def _run_calls(batch, insts, shapes, calls, seed, check_oracle=False, between=None):
     import torch
 
     rng = np.random.default_rng(seed)
-    for r in range(rounds):
+    for r in range(calls):
         pert = _perturbations(shapes, rng)
         lam_before = [(_read(a, u.lam.size)[:2]) for u, a, _ in insts] if check_oracle else None
         batch.update([(a, Kt, sig) for (u, a, _), (Kt, sig, _) in zip(insts, pert)])
@@ -107,7 +107,7 @@ def test_uneven_batch_matches_single_updates():
     print("case uneven batch, 8 instances", flush=True)
     insts = _make_pairs(SHAPES, 500)
     with eu.EigBatch(16, 0) as batch:
-        _run_rounds(batch, insts, SHAPES, 1, seed=9, check_oracle=True)
+        _run_calls(batch, insts, SHAPES, 1, seed=9, check_oracle=True)
     _close(insts)
 
 
@@ -125,9 +125,9 @@ def test_graph_replays_match_every_time():
         torch.cuda.synchronize()
 
     with eu.EigBatch(16, 0) as batch:
-        _run_rounds(batch, insts, SHAPES, 6, seed=10, between=eager)
-        # rounds 1-2 tune (one candidate each), round 3 runs direct, round 4
-        # captures the graph and launches it, rounds 5-6 replay it
+        _run_calls(batch, insts, SHAPES, 6, seed=10, between=eager)
+        # batch calls 1-2 tune (one candidate each), call 3 runs direct, call 4
+        # captures the graph and launches it, calls 5-6 replay it
         assert batch.get(eu.EIG_KNOB_GRAPHS) == 1
         assert batch.get(eu.EIG_STAT_GRAPH_LAUNCHES) >= 3
         assert batch.get(eu.EIG_STAT_GRAPHS_CACHED) == 1
@@ -147,7 +147,7 @@ def test_forced_knobs_are_bitwise_neutral(root, tile, graphs):
         batch.set(eu.EIG_KNOB_ROOTSOLVE, root)
         batch.set(eu.EIG_KNOB_GEMM_TILE, tile)
         batch.set(eu.EIG_KNOB_GRAPHS, graphs)
-        _run_rounds(batch, insts, shapes, 3, seed=11)
+        _run_calls(batch, insts, shapes, 3, seed=11)
         assert batch.get(eu.EIG_KNOB_ROOTSOLVE) == root
         assert batch.get(eu.EIG_KNOB_GEMM_TILE) == tile
     _close(insts)
