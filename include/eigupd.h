@@ -113,13 +113,26 @@ enum {
   EIG_HOST_INPUT = 1 << 6,  /* K is a host pointer (copied before return) */
   EIG_PHASE_TIMING = 1 << 7, /* record HIP events between the phases on hip_stream;
                                 eig_query reports the times in eig_info.ms */
-  EIG_LOCATE_RESIDUES = 1 << 8 /* k = 2: locate the roots by the signs of the
+  EIG_LOCATE_RESIDUES = 1 << 8, /* k = 2: locate the roots by the signs of the
                                   residues alpha_i (Sec. 2.2, eq. (2), Alg. 1a-1c)
                                   instead of the inertia pole counts; taken only
                                   when every pole is simple and every residue is
                                   larger than its rounding bound, else the pole
                                   counts run (eig_info.located_by_residues tells
                                   which); ignored for k != 2 */
+  EIG_QW_FARFIELD = 1 << 9  /* FP64, n >= 2048: form Q' = Q W with the far blocks
+                               of W (Sec. 2.4, eq. (10)) replaced by Chebyshev
+                               expansions of 1/(x - y) (blocks of 256 rows and
+                               columns, 24 nodes per interval): a band of exact
+                               block products plus three small products, about
+                               8x fewer flops at n = 8192.  Q' agrees with the
+                               dense product to rounding level (the interpolation
+                               error is below 1e-15 for blocks at least half
+                               their width apart).  Falls back to the dense
+                               product on the device when the update merged
+                               equal poles; ignored for n < 2048 and with the
+                               reduced-precision modes.  Allocates its buffers
+                               (about 2 k n^2 P / 256 doubles) on first use. */
 };
 
 enum { EIG_KMAX = 8 };

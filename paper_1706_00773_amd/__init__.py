@@ -40,6 +40,7 @@ EIG_VALUES_ONLY = 1 << 4
 EIG_HOST_INPUT = 1 << 6
 EIG_PHASE_TIMING = 1 << 7
 EIG_LOCATE_RESIDUES = 1 << 8
+EIG_QW_FARFIELD = 1 << 9
 EIG_KMAX = 8
 
 EIG_DBG_U = 1

@@ -198,6 +198,7 @@ int eig_state_destroy(eig_state_t s) {
       if (e) (void)hipEventDestroy(e);
     if (s->block) (void)hipFree(s->block);
     if (s->lp_block) (void)hipFree(s->lp_block);
+    if (s->ff_block) (void)hipFree(s->ff_block);
   }
   delete s;
   return EIG_OK;
@@ -240,7 +241,7 @@ int eig_update_rankk(eig_state_t s, int64_t k, const double* K, int64_t ldk, con
   if (k > EIG_KMAX) return EIG_EUNSUPPORTED;
   if (k > s->n) return EIG_EINVAL;
   const uint32_t known = EIG_GEMM_MASK | EIG_VALUES_ONLY | EIG_HOST_INPUT | EIG_PHASE_TIMING |
-                         EIG_LOCATE_RESIDUES;
+                         EIG_LOCATE_RESIDUES | EIG_QW_FARFIELD;
   if (mode & ~known) return EIG_EUNSUPPORTED;
   const int prec = (int)(mode & EIG_GEMM_MASK);
   if (prec != EIG_GEMM_FP64 && prec != EIG_GEMM_FP32_CORR && prec != EIG_GEMM_BF16X3_CORR)
@@ -299,6 +300,26 @@ int eig_update_rankk(eig_state_t s, int64_t k, const double* K, int64_t ldk, con
       s->lp_bytes = need;
     }
   }
+  const bool farfield = (mode & EIG_QW_FARFIELD) && prec == EIG_GEMM_FP64 && !vo &&
+                        ff_eligible((int)n, (int)k);
+  if (farfield) {
+    const size_t need = ff_bytes((int)n, (int)k);
+    if (s->ff_bytes < need) {
+      if (s->ff_block) {
+        HIPCHK(hipStreamSynchronize(st));
+        HIPCHK(hipDeviceSynchronize());
+        (void)hipFree(s->ff_block);
+        s->ff_block = nullptr;
+        s->ff_bytes = 0;
+      }
+      if (hipMalloc(&s->ff_block, need) != hipSuccess) {
+        (void)hipGetLastError();
+        s->ff_block = nullptr;
+        return EIG_ENOMEM;
+      }
+      s->ff_bytes = need;
+    }
+  }
   HIPCHK(mark(0));
   if (prec == EIG_GEMM_FP64)
     HIPCHK(launch_qtk(w, st));
@@ -330,7 +351,9 @@ int eig_update_rankk(eig_state_t s, int64_t k, const double* K, int64_t ldk, con
   HIPCHK(launch_wbuild(w, st));
   HIPCHK(launch_group_reflect(w, st));
   HIPCHK(mark(5));
-  if (prec == EIG_GEMM_FP64)
+  if (farfield)
+    HIPCHK(launch_qw_farfield(w, ff_layout(s->ff_block, (int)n, (int)k), st));
+  else if (prec == EIG_GEMM_FP64)
     HIPCHK(launch_dgemm((int)n, (int)n, (int)n, w.Q_in, (int)n, w.W, (int)n, w.Q_out, (int)n,
                         &w.st->status, st));
   else

@@ -44,7 +44,8 @@ __device__ __forceinline__ void tile_of(int bid, int tiles_m, int tiles_n, int* 
 // doubles of the A slice (pairs of rows 32 apart in one k-column) and BT/16 of
 // the B slice (consecutive k of one column of B).  Every tile size runs the
 // same k-slices in the same order, so C is bitwise the same for any BT.
-template <int BT>
+// ACC: C += A B instead of C = A B.
+template <int BT, bool ACC = false>
 __device__ __forceinline__ void dgemm_tile(int M, int N, int Kd, const double* __restrict__ A,
                                            int lda, const double* __restrict__ B, int ldb,
                                            double* __restrict__ C, int ldc, int tm, int tn,
@@ -161,7 +162,12 @@ __device__ __forceinline__ void dgemm_tile(int M, int N, int Kd, const double* _
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           const int row = m0 + wm + i * 16 + fk + 4 * v;
-          if (row < M) dst[row] = acc[i][j][v];
+          if (row < M) {
+            if constexpr (ACC)
+              dst[row] += acc[i][j][v];
+            else
+              dst[row] = acc[i][j][v];
+          }
         }
       }
     }
@@ -202,6 +208,40 @@ __global__ __launch_bounds__(GNT, 2) void dgemm_group(const GemmDesc* __restrict
   const int gsz = min(tiles - first_m, GGROUP);
   const int in = t % tpg;
   dgemm_tile<BT>(g.n, g.n, g.n, g.A, g.n, g.B, g.n, g.C, g.n, first_m + in % gsz, in / gsz, g.vec);
+}
+
+// Products of general shapes from device-built descriptors: block b is tile
+// b - prefix[i] of instance i, tiles ordered down the columns of C.  Skipped on
+// the device when *skip != 0.
+template <bool ACC>
+__global__ __launch_bounds__(GNT, 2) void dgemm_desc(const GemmDescG* __restrict__ d,
+                                                     const int* __restrict__ prefix, int ninst,
+                                                     const int32_t* skip) {
+  if (__builtin_nontemporal_load(skip) != 0) return;
+  int lo = 0, hi = ninst - 1;
+  const int b = blockIdx.x;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (prefix[mid] <= b)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  const GemmDescG& g = d[lo];
+  if (g.M <= 0 || g.N <= 0 || g.K <= 0) return;  // an empty instance
+  const int t = b - prefix[lo];
+  dgemm_tile<GBM, ACC>(g.M, g.N, g.K, g.A, g.lda, g.B, g.ldb, g.C, g.ldc, t % g.tiles_m,
+                       t / g.tiles_m, g.vec);
+}
+
+hipError_t launch_dgemm_desc(bool acc, const GemmDescG* d, const int* prefix, int ninst,
+                             int blocks, const int32_t* skip, hipStream_t s) {
+  if (blocks <= 0) return hipSuccess;
+  if (acc)
+    hipLaunchKernelGGL((dgemm_desc<true>), dim3(blocks), dim3(GNT), 0, s, d, prefix, ninst, skip);
+  else
+    hipLaunchKernelGGL((dgemm_desc<false>), dim3(blocks), dim3(GNT), 0, s, d, prefix, ninst, skip);
+  return hipGetLastError();
 }
 
 int gemm_tiles(int n, int bt) {

@@ -167,6 +167,41 @@ struct GemmDesc {
   int vec;
 };
 
+// One product C (+)= A B of a general shape, column-major, built on the device;
+// tiles_m = ceil(M / 128); vec: 16-byte accesses allowed.
+struct GemmDescG {
+  const double* A;
+  const double* B;
+  double* C;
+  int M, N, K, lda, ldb, ldc, vec, tiles_m;
+};
+
+// Q' = Q W with the far blocks of W from Chebyshev expansions (farfield.hip):
+// buffers of one state, laid out by ff_layout in ff_bytes(n, k) bytes.
+struct FarField {
+  int n, k, nb, pad;
+  double* M;      // (k n) x (nb P) expansions of the row blocks
+  double* L;      // (k n) x (nb P) expansions at the column blocks
+  double* T;      // (nb P) x (nb P) interaction matrix
+  double* B;      // row-block weights, b_J x kP each
+  double* Phi;    // kP x n column weights
+  double* iv;     // 4 per block: pole interval, column-point interval
+  double* xn;     // nb P column-block nodes
+  double* yn;     // nb P row-block nodes
+  GemmDescG* desc;  // 7 nb: near band, P2M, L2P, four rounds of extra near pairs
+  int* prefix;    // 7 (nb + 1) tile offsets
+  int* near;      // 2 nb: first and last row block of each near band
+  int* extra;     // 4 nb: row blocks of the extra near pairs of each column block (-1: none)
+  int* flags;     // [0] far path skipped, [1] dense path skipped
+};
+bool ff_eligible(int n, int k);
+int ff_blocks(int n);
+size_t ff_bytes(int n, int k);
+FarField ff_layout(void* base, int n, int k);
+// Enqueues the plan, both product paths (one of them exits at once) and leaves
+// Q_out = Q_in W.  Needs finalize and wbuild to have run.
+hipError_t launch_qw_farfield(const Work& w, const FarField& f, hipStream_t s);
+
 // Launchers (stream-ordered, no allocation).
 hipError_t launch_qtk(const Work& w, hipStream_t s);
 hipError_t launch_deflate(const Work& w, hipStream_t s);
@@ -191,6 +226,10 @@ hipError_t launch_perturb_w(const Work& w, double* lam_out, hipStream_t s);
 // C = A * B, column-major, FP64 MFMA.  Skipped on the device when *status != 0.
 hipError_t launch_dgemm(int M, int N, int Kd, const double* A, int lda, const double* B, int ldb,
                         double* C, int ldc, const int32_t* status, hipStream_t s);
+// Products from ninst device-built descriptors (acc: C += A B); block b of the
+// grid is tile b - prefix[i] of instance i; skipped on the device when *skip != 0.
+hipError_t launch_dgemm_desc(bool acc, const GemmDescG* d, const int* prefix, int ninst,
+                             int blocks, const int32_t* skip, hipStream_t s);
 // Grouped launches over `ninst` instances of one rank k (blocks = total blocks,
 // Group.prefix built from the per-instance counts below).
 int qtk_blocks(int n, int k);

@@ -17,6 +17,8 @@ struct eig_state_s {
   double* Kbuf = nullptr;
   void* lp_block = nullptr;  // slice planes of the reduced-precision modes (lazily)
   size_t lp_bytes = 0;
+  void* ff_block = nullptr;  // buffers of the far-field product (lazily)
+  size_t ff_bytes = 0;
   eigupd::Work w{};       // workspace pointers (carved from block)
   hipEvent_t ev[9] = {};  // phase events (EIG_PHASE_TIMING)
   bool timed = false;

@@ -1,0 +1,182 @@
+"""GPU parity of the far-field product Q' = Q W (EIG_QW_FARFIELD).
+
+The mode changes only how Q W is formed, so:
+- its eigenvalues must be bitwise those of the dense path;
+- its Q' must agree with the dense product entrywise within 1e-12 (the
+  Chebyshev interpolation error of 1/(x - y) on blocks at least half their width
+  apart is below 1e-15 relative; the margin covers sums over n = 8192 terms of
+  entries below 1);
+- against the oracle's matrix A' it must meet the tolerances of every update
+  (eigenvalues 1e-10 ||A'||, residual 1e-9 ||A'||, ||Q'^T Q' - I||_max 1e-9).
+Where the plan must fall back (merged equal poles), where every column block
+has too many close row blocks for the expansions (then each is multiplied
+exactly over all rows), or where the mode does not apply (n < 2048), the
+result must be bitwise the dense one.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import paper_1706_00773_amd as eu
+from paper_1706_00773_amd import workloads as wl
+
+from helpers import colmajor, run_update
+
+pytestmark = pytest.mark.gpu
+
+DIFF_TOL = 1e-12
+EVAL_TOL = 1e-10
+RES_TOL = 1e-9
+ORTH_TOL = 1e-9
+FF = eu.EIG_QW_FARFIELD
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    eu.load_library()
+
+
+def _both(u):
+    lam, Q, K, sig = np.asarray(u.lam), np.asarray(u.Q), np.asarray(u.K), u.sigma
+    ld, Qd, _, _ = run_update(lam, Q, K, sig)
+    lf, Qf, info, _ = run_update(lam, Q, K, sig, prec=FF)
+    return ld, Qd, lf, Qf, info
+
+
+def _check_oracle(u, lo, Qo):
+    A = wl.explicit_matrix(u.lam, u.Q, u.K, u.sigma)
+    U = oracle.qtk(np.asfortranarray(np.asarray(u.Q)), np.asarray(u.K))
+    ref = np.sort(oracle.eigvals(np.asarray(u.lam), U, u.sigma)[0])
+    scale = np.abs(ref).max()
+    n = lo.size
+    assert np.abs(lo - ref).max() <= EVAL_TOL * scale
+    assert np.abs(A @ Qo - Qo * lo).max() <= RES_TOL * scale
+    assert np.abs(Qo.T @ Qo - np.eye(n)).max() <= ORTH_TOL
+
+
+CASES = [
+    ("rank2 e_j a^T + a e_j^T, n=2048", lambda: wl.plain_rank2(2048, seed=31, min_gap=1e-12)),
+    ("ragged n=2500 (last block 452), k=3", lambda: wl.random_small(2500, 3, seed=32)),
+    ("k=1, n=2304", lambda: wl.general_rankk(1, n=2304, seed=33)),
+    ("k=5, n=2304", lambda: wl.general_rankk(5, n=2304, seed=34)),
+    ("k=8, n=2048", lambda: wl.general_rankk(8, n=2048, seed=35)),
+    ("clusters and tiny rows, n=4096", lambda: wl.clustered_rank2(4096, seed=36)),
+]
+
+
+@pytest.mark.parametrize("name,make", CASES, ids=[c[0] for c in CASES])
+def test_farfield_matches_dense_and_oracle(name, make):
+    print(f"case farfield {name}", flush=True)
+    u = make()
+    ld, Qd, lf, Qf, info = _both(u)
+    assert np.array_equal(ld, lf)
+    assert np.abs(Qf - Qd).max() <= DIFF_TOL
+    _check_oracle(u, lf, Qf)
+
+
+def test_farfield_chained_updates():
+    import torch
+
+    print("case farfield chained n=2048 k=2", flush=True)
+    n, dev = 2048, "cuda:0"
+    u = wl.random_small(n, 2, seed=40)
+    rng = np.random.default_rng(41)
+    Ks = [rng.standard_normal((n, 2)) / np.sqrt(n) for _ in range(3)]
+    outs = []
+    for mode in (0, FF):
+        with eu.EigState(n, 0) as s:
+            s.upload(torch.as_tensor(u.lam, device=dev), colmajor(u.Q, dev))
+            for K in Ks:
+                s.update(colmajor(K, dev), np.array([1, -1]), mode)
+            lo = torch.empty(n, dtype=torch.float64, device=dev)
+            Qo = torch.empty((n, n), dtype=torch.float64, device=dev).t()
+            s.query(lo, Qo)
+            outs.append((lo.cpu().numpy(), Qo.cpu().numpy()))
+    (ld, Qd), (lf, Qf) = outs
+    assert np.abs(lf - ld).max() <= 1e-13 * np.abs(ld).max()
+    assert np.abs(Qf - Qd).max() <= DIFF_TOL
+    assert np.abs(Qf.T @ Qf - np.eye(n)).max() <= ORTH_TOL
+
+
+def test_equal_poles_fall_back_to_the_dense_product():
+    print("case farfield fallback with equal-pole groups n=2048", flush=True)
+    n, k = 2048, 2
+    rng = np.random.default_rng(42)
+    lam = np.sort(rng.uniform(-1, 1, n))
+    lam[700:704] = lam[700]
+    lam = np.sort(lam)
+    Q = wl.orthogonal_from(rng.standard_normal((n, n)))
+    K = np.asfortranarray(rng.standard_normal((n, k)) / np.sqrt(n))
+    sig = np.array([1, -1], dtype=np.int8)
+    ld, Qd, info, _ = run_update(lam, Q, K, sig)
+    lf, Qf, info_f, _ = run_update(lam, Q, K, sig, prec=FF)
+    assert info_f.n_deflated_groups == 1
+    assert np.array_equal(ld, lf) and np.array_equal(Qd, Qf)
+
+
+def test_widely_spread_spectrum_is_multiplied_exactly():
+    """lambda = +-10^U[-3, 3]: blocks of 256 consecutive eigenvalues span decades,
+    so every column block has more close row blocks than extra near products and
+    takes all rows exactly: the same sums as the dense product."""
+    print("case farfield fallback with a log-spread spectrum n=2048 k=4", flush=True)
+    u = wl.logspread_rankk(4, n=2048, seed=50)
+    ld, Qd, lf, Qf, _ = _both(u)
+    assert np.array_equal(ld, lf) and np.array_equal(Qd, Qf)
+
+
+def test_small_order_ignores_the_mode():
+    print("case farfield below the size threshold n=600", flush=True)
+    u = wl.random_small(600, 3, seed=43)
+    ld, Qd, lf, Qf, _ = _both(u)
+    assert np.array_equal(ld, lf) and np.array_equal(Qd, Qf)
+
+
+def test_values_only_and_reduced_precision_ignore_the_mode():
+    print("case farfield with values-only and FP32 modes n=2048", flush=True)
+    u = wl.random_small(2048, 2, seed=44)
+    lam, Q, K, sig = np.asarray(u.lam), np.asarray(u.Q), np.asarray(u.K), u.sigma
+    lv, _, _, _ = run_update(lam, Q, K, sig, values_only=True)
+    lvf, _, _, _ = run_update(lam, Q, K, sig, values_only=True, prec=FF)
+    assert np.array_equal(lv, lvf)
+    l32, Q32, _, _ = run_update(lam, Q, K, sig, prec=eu.EIG_GEMM_FP32_CORR)
+    l32f, Q32f, _, _ = run_update(lam, Q, K, sig, prec=eu.EIG_GEMM_FP32_CORR | FF)
+    assert np.array_equal(l32, l32f) and np.array_equal(Q32, Q32f)
+
+
+def test_headline_size_n8192():
+    """n = 8192, k = 2 in the benchmark's workload: entrywise against the dense
+    product, and residual and orthogonality against A' on 256 sampled columns."""
+    import torch
+
+    print("case farfield headline n=8192", flush=True)
+    n, dev = 8192, "cuda:0"
+    u = wl.headline(n, device=dev)
+    outs = []
+    for mode in (0, FF):
+        with eu.EigState(n, 0) as s:
+            s.upload(torch.as_tensor(np.asarray(u.lam), device=dev), u.Q)
+            s.update(colmajor(np.asarray(u.K.cpu() if isinstance(u.K, torch.Tensor) else u.K), dev),
+                     u.sigma, mode)
+            lo = torch.empty(n, dtype=torch.float64, device=dev)
+            Qo = torch.empty((n, n), dtype=torch.float64, device=dev).t()
+            s.query(lo, Qo)
+            outs.append((lo, Qo))
+    (ld, Qd), (lf, Qf) = outs
+    assert torch.equal(ld, lf)
+    assert float((Qf - Qd).abs().max()) <= DIFF_TOL
+    cols = np.random.default_rng(45).choice(n, 256, replace=False)
+    Qs = Qf[:, cols].cpu().numpy()
+    Qh = u.Q.cpu().numpy() if isinstance(u.Q, torch.Tensor) else np.asarray(u.Q)
+    Kh = u.K.cpu().numpy() if isinstance(u.K, torch.Tensor) else np.asarray(u.K)
+    lam = np.asarray(u.lam.cpu() if isinstance(u.lam, torch.Tensor) else u.lam)
+    lv = lf.cpu().numpy()[cols]
+    Aq = Qh @ (lam[:, None] * (Qh.T @ Qs)) + Kh @ (np.asarray(u.sigma, float)[:, None] * (Kh.T @ Qs))
+    scale = np.abs(lf.cpu().numpy()).max()
+    assert np.abs(Aq - Qs * lv).max() <= RES_TOL * scale
+    G = (Qf.t() @ Qf[:, cols]).cpu().numpy()
+    G[cols, np.arange(cols.size)] -= 1.0
+    assert np.abs(G).max() <= ORTH_TOL
