@@ -567,19 +567,35 @@ def perturbation_sweep(args, dev):
             "rows": rows}
 
 
-def measured_traffic():
-    """HBM bytes per launch of the GEMM from the rocprofv3 FETCH_SIZE / WRITE_SIZE runs
-    recorded under profiles/, or None once gemm.hip differs from the measured source."""
+def measured_traffic(path_name, sources):
+    """HBM bytes per update of the Q W step from the rocprofv3 FETCH_SIZE / WRITE_SIZE
+    runs recorded under profiles/, or None once a source differs from the measured one."""
     import hashlib
 
-    path = os.path.join(ROOT, "profiles", "dgemm_rank2_n8192_traffic.json")
-    src = os.path.join(ROOT, "paper_1706_00773_amd", "csrc", "gemm.hip")
+    path = os.path.join(ROOT, "profiles", path_name)
     try:
         rec = json.load(open(path))
-        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+        h = hashlib.sha256()
+        for src in sources:
+            h.update(open(os.path.join(ROOT, "paper_1706_00773_amd", "csrc", src), "rb").read())
     except (OSError, ValueError):
         return None
-    return rec["traffic_bytes"] if rec.get("gemm_source_sha256") == sha else None
+    return rec["traffic_bytes"] if rec.get("sources_sha256") == h.hexdigest() else None
+
+
+# Block size and Chebyshev nodes of the library's far-field product (farfield.hip).
+FF_B, FF_P = 256, 24
+
+
+def farfield_flops(n, k):
+    """Algorithmic flops of Q W by the far-field product: the exact band of row
+    blocks I-1..I+1 per column block, P2M (2 n^2 kP), M2L (2 kn (nb P)^2) and L2P
+    (2 n^2 kP).  The extra near pairs the plan may add are not counted."""
+    nb = n // FF_B
+    size = [FF_B] * (nb - 1) + [n - (nb - 1) * FF_B]
+    band = sum(2.0 * n * size[i] * sum(size[max(0, i - 1):min(nb, i + 2)]) for i in range(nb))
+    kp = k * FF_P
+    return band + 2.0 * n * n * kp + 2.0 * k * n * (nb * FF_P) ** 2 + 2.0 * n * n * kp
 
 
 def main():
@@ -600,6 +616,11 @@ def main():
     ap.add_argument("--load-input", metavar="NPZ",
                     help="read the resident decomposition from NPZ (written by --save-input) "
                          "instead of generating it")
+    ap.add_argument("--qw", choices=["farfield", "dense"], default="farfield",
+                    help="how Q' = Q W is formed: far-field product (EIG_QW_FARFIELD) or "
+                         "the dense FP64 product")
+    ap.add_argument("--no-dense-compare", action="store_true",
+                    help="with --qw farfield: skip the dense comparison pass")
     ap.add_argument("--locate-residues", action="store_true",
                     help="k = 2: locate roots by residue signs (EIG_LOCATE_RESIDUES)")
     ap.add_argument("--precision", action="store_true",
@@ -698,6 +719,9 @@ def main():
     torch.cuda.synchronize()
 
     umode = eu.EIG_LOCATE_RESIDUES if args.locate_residues else 0
+    farfield = args.qw == "farfield" and n >= 2048
+    if farfield:
+        umode |= eu.EIG_QW_FARFIELD
     log(f"[bench] warmup {warm}")
     for s in range(warm):
         state.update(perts[s][0], perts[s][1], umode)
@@ -732,19 +756,43 @@ def main():
         phases.append(list(inf.ms))
     phases = np.array(phases)
     gemm_ms = float(phases[:, 5].mean())
-    gemm_flops = 2.0 * n ** 3
-    achieved = gemm_flops / (gemm_ms * 1e-3) / 1e12
-    roofline = {
-        "kernel": "dgemm_kernel (Q' = Q W, FP64 MFMA 16x16x4)",
-        "bound": "mfma",
-        "achieved": round(achieved, 3),
-        "peak": PEAK_FP64_MFMA_TFLOPS,
-        "unit": "TFLOP/s",
-        "frac": round(achieved / PEAK_FP64_MFMA_TFLOPS, 4),
-        "traffic": (measured_traffic() if (n, k) == (8192, 2) else None),
-        "avg_ms": round(gemm_ms, 4),
-        "algorithmic": f"2 n^3 = {gemm_flops:.3e} flop per launch",
-    }
+
+    def dense_roofline(ms):
+        flops = 2.0 * n ** 3
+        ach = flops / (ms * 1e-3) / 1e12
+        return {
+            "kernel": "dgemm_kernel (Q' = Q W, FP64 MFMA 16x16x4)",
+            "bound": "mfma",
+            "achieved": round(ach, 3),
+            "peak": PEAK_FP64_MFMA_TFLOPS,
+            "unit": "TFLOP/s",
+            "frac": round(ach / PEAK_FP64_MFMA_TFLOPS, 4),
+            "traffic": (measured_traffic("qw_dense_rank2_n8192_traffic.json", ["gemm.hip"])
+                        if (n, k) == (8192, 2) else None),
+            "avg_ms": round(ms, 4),
+            "algorithmic": f"2 n^3 = {flops:.3e} flop per launch",
+        }
+
+    if farfield:
+        ff_flops = farfield_flops(n, k)
+        achieved = ff_flops / (gemm_ms * 1e-3) / 1e12
+        roofline = {
+            "kernel": ("Q' = Q W far-field product (exact band, P2M, M2L, L2P: dgemm_desc and "
+                       "dgemm_kernel launches on FP64 MFMA 16x16x4, timed together)"),
+            "bound": "mfma",
+            "achieved": round(achieved, 3),
+            "peak": PEAK_FP64_MFMA_TFLOPS,
+            "unit": "TFLOP/s",
+            "frac": round(achieved / PEAK_FP64_MFMA_TFLOPS, 4),
+            "traffic": (measured_traffic("qw_farfield_rank2_n8192_traffic.json",
+                                         ["gemm.hip", "farfield.hip"])
+                        if (n, k) == (8192, 2) else None),
+            "avg_ms": round(gemm_ms, 4),
+            "algorithmic": (f"band + P2M + M2L + L2P = {ff_flops:.3e} flop per update "
+                            f"(dense 2 n^3 = {2.0 * n ** 3:.3e})"),
+        }
+    else:
+        roofline = dense_roofline(gemm_ms)
     names = ["qtk", "deflate", "polecount+locate", "rootsolve+rootvec", "finalize+wbuild",
              "dgemm", "commit", "total"]
     phase_ms = {nm: round(float(phases[:, i].mean()), 4) for i, nm in enumerate(names)}
@@ -759,7 +807,8 @@ def main():
     ideal = {"qtk": (8.0 * n * n + 16.0 * n * k) / (PEAK_HBM_GBS * 1e9) * 1e3,
              "roots": root_flop / (PEAK_FP64_VALU_TFLOPS * 1e12) * 1e3,
              "wbuild": 8.0 * n * n / (PEAK_HBM_GBS * 1e9) * 1e3,
-             "dgemm": 2.0 * n ** 3 / (PEAK_FP64_MFMA_TFLOPS * 1e12) * 1e3}
+             "dgemm": (farfield_flops(n, k) if farfield else 2.0 * n ** 3)
+             / (PEAK_FP64_MFMA_TFLOPS * 1e12) * 1e3}
     ideal_ms = sum(ideal.values())
     whole = {"ideal_ms": round(ideal_ms, 3), "measured_ms": round(ms_per_step, 3),
              "frac": round(ideal_ms / ms_per_step, 4),
@@ -799,9 +848,30 @@ def main():
         "location": ("residue signs (Alg. 1), %d of %d updates" % (sum(located), len(located))
                      if args.locate_residues else "inertia pole counts"),
         "orth_sample_max": orth,
+        "qw": ("far-field product (EIG_QW_FARFIELD)" if farfield else "dense FP64 product"),
         "roofline": roofline,
         "roofline_whole_update": whole,
     }
+
+    if farfield and not args.no_dense_compare:
+        # the dense product on the same chained state, for comparison
+        log(f"[bench] dense Q W for comparison: {steps} chained updates")
+        dmode = umode & ~eu.EIG_QW_FARFIELD
+        dperts = make_perturbations(n, k, steps, seed=2500, dev=dev)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for K, sig in dperts:
+            state.update(K, sig, dmode)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        state.query()
+        d_ms = e0.elapsed_time(e1) / steps
+        d_ph = []
+        for K, sig in dperts[: max(3, steps // 4)]:
+            state.update(K, sig, dmode | eu.EIG_PHASE_TIMING)
+            d_ph.append(state.query().ms[5])
+        result["dense_qw"] = {"updates_per_s": round(1000.0 / d_ms, 4), "ms_per_step": round(d_ms, 4),
+                              "roofline": dense_roofline(float(np.mean(d_ph)))}
 
     if not args.no_reeigh:
         log("[bench] re-eigh baseline: torch.linalg.eigh FP64 on the same GPU")
@@ -821,7 +891,7 @@ def main():
         # the same A' through the update path
         chk = eu.EigState(n, 0)
         chk.upload(lam_t, Q0)
-        chk.update(Kt, sig)
+        chk.update(Kt, sig, umode & eu.EIG_QW_FARFIELD)
         lam_u = torch.empty(n, dtype=torch.float64, device=dev)
         Q_u = torch.empty((n, n), dtype=torch.float64, device=dev).t()
         chk.query(lam_u, Q_u)
