@@ -17,12 +17,12 @@
 //     M2L  L = M T                     (T zero on the near pairs)
 //     L2P  Q'(:, I) += L_I Phi_I,      Phi_I((l, a), p) = S_{I,l}(x_p) c_{p,a}
 // The near blocks are multiplied exactly: the band of row blocks I-1..I+1 around
-// each column block, Q'(:, I) = Q(:, band) W(band, I), plus up to FF_XR further
-// pairs whose intervals are not far apart (a block widened by an outlying pole
-// or root), each added as Q'(:, I) += Q(:, J) W(J, I) in rounds that touch every
-// column block at most once.  A column block with more such pairs takes all
-// rows as its band (no far field).  Deflated columns (unit vectors) lie in the
-// band; deflated rows carry no charge.
+// each column block, Q(:, band) W(band, I), plus up to FF_XR further pairs whose
+// intervals are not far apart (a block widened by an outlying pole or root),
+// Q(:, J) W(J, I).  Band, extra pairs and L2P are the segments of one product per
+// column block, summed in registers and stored once.  A column block with more
+// such pairs takes all rows as its band (no far field).  Deflated columns (unit
+// vectors) lie in the band; deflated rows carry no charge.
 //
 // Layouts (column-major): M and L are (k n) x (nb P) with row (a, r) at a n + r,
 // so that the columns (m, a) of one block form an n x kP matrix of leading
@@ -43,8 +43,7 @@ constexpr int FF_P = 24;         // Chebyshev nodes per interval
 constexpr double FF_ETA = 0.5;   // far: distance >= FF_ETA * max(width_I, width_J)
 constexpr int FF_MIN_N = 2048;   // below this the dense product is used
 constexpr int FF_TILE = 128;     // tile side of the descriptor products
-constexpr int FF_XR = 4;         // extra near pairs per column block (rounds)
-constexpr int FF_ND = 3 + FF_XR; // descriptor sets: band, P2M, L2P, extra rounds
+constexpr int FF_XR = GSEG - 2;  // extra near pairs per column block
 
 int ff_blocks(int n) { return n / FF_B; }
 __host__ __device__ static inline int ff_bsize(int n, int nb, int i) {
@@ -61,8 +60,8 @@ size_t ff_bytes(int n, int k) {
              + 2 * (size_t)n * kp      // B, Phi
              + 4 * nb + 2 * np;        // intervals, nodes
   size_t bytes = d * sizeof(double);
-  bytes += FF_ND * nb * sizeof(GemmDescG) +
-           (FF_ND * (nb + 1) + 2 * nb + FF_XR * nb + 4) * sizeof(int);
+  bytes += nb * sizeof(GemmDescG) + nb * sizeof(GemmSegDesc) +
+           (2 * (nb + 1) + 2 * nb + FF_XR * nb + 4) * sizeof(int);
   return bytes + 256;
 }
 
@@ -91,10 +90,13 @@ FarField ff_layout(void* base, int n, int k) {
   d += np;
   GemmDescG* g = reinterpret_cast<GemmDescG*>(d);
   f.desc = g;
-  g += FF_ND * nb;
-  int* ip = reinterpret_cast<int*>(g);
+  g += nb;
+  GemmSegDesc* sg = reinterpret_cast<GemmSegDesc*>(g);
+  f.seg = sg;
+  sg += nb;
+  int* ip = reinterpret_cast<int*>(sg);
   f.prefix = ip;
-  ip += FF_ND * (nb + 1);
+  ip += 2 * (nb + 1);
   f.near = ip;
   ip += 2 * nb;
   f.extra = ip;
@@ -235,32 +237,57 @@ __global__ __launch_bounds__(256) void ff_plan_kernel(Work w, FarField f) {
       f.xn[I * FF_P + m] = ok ? ff_node(f.iv[4 * I + 2], f.iv[4 * I + 3], m) : 0.0;
     }
     const int k0 = lo * FF_B, kn = (hi + 1 == nb ? n : (hi + 1) * FF_B) - k0;
-    // band: Q'(:, I) = Q(:, band rows) W(band rows, I)
-    f.desc[I] = ff_desc(w.Q_in + (size_t)k0 * n, n, w.W + (size_t)r0 * n + k0, n,
-                        w.Q_out + (size_t)r0 * n, n, n, b, kn);
     // P2M: M_I = Q(:, I) B_I
-    f.desc[nb + I] = ff_desc(w.Q_in + (size_t)r0 * n, n, f.B + (size_t)r0 * kp, b,
-                             f.M + (size_t)I * FF_P * k * n, n, n, kp, b);
-    // L2P: Q'(:, I) += L_I Phi_I
-    f.desc[2 * nb + I] = ff_desc(f.L + (size_t)I * FF_P * k * n, n, f.Phi + (size_t)r0 * kp, kp,
-                                 w.Q_out + (size_t)r0 * n, n, n, b, kp);
-    // extra near pairs: Q'(:, I) += Q(:, J) W(J, I), one per round (K = 0: none)
+    f.desc[I] = ff_desc(w.Q_in + (size_t)r0 * n, n, f.B + (size_t)r0 * kp, b,
+                        f.M + (size_t)I * FF_P * k * n, n, n, kp, b);
+    // Q'(:, I) = Q(:, band) W(band, I) + sum_extra Q(:, J) W(J, I) + L_I Phi_I
+    GemmSegDesc& g = f.seg[I];  // written in place
+    int ns = 0, sl = 0;
+    bool vec = !(n & 1) && !(kp & 1);
+    auto add = [&](const double* A, const double* B, int ldb, int K) {
+      g.A[ns] = A;
+      g.B[ns] = B;
+      g.lda[ns] = n;
+      g.ldb[ns] = ldb;
+      g.K[ns] = K;
+      sl += (K + 15) / 16;
+      g.send[ns] = sl;
+      vec = vec && !((uintptr_t)A & 15) && !((uintptr_t)B & 15);
+      ++ns;
+    };
+    add(w.Q_in + (size_t)k0 * n, w.W + (size_t)r0 * n + k0, n, kn);
     for (int r = 0; r < FF_XR; ++r) {
       const int J = ok ? f.extra[I * FF_XR + r] : -1;
-      const int j0 = J >= 0 ? J * FF_B : 0, bj = J >= 0 ? ff_bsize(n, nb, J) : 0;
-      f.desc[(3 + r) * nb + I] = ff_desc(w.Q_in + (size_t)j0 * n, n, w.W + (size_t)r0 * n + j0, n,
-                                         w.Q_out + (size_t)r0 * n, n, n, b, bj);
+      if (J >= 0) {
+        const int j0 = J * FF_B;
+        add(w.Q_in + (size_t)j0 * n, w.W + (size_t)r0 * n + j0, n, ff_bsize(n, nb, J));
+      }
     }
+    add(f.L + (size_t)I * FF_P * k * n, f.Phi + (size_t)r0 * kp, kp, kp);
+    for (int r = ns; r < GSEG; ++r) {
+      g.A[r] = g.B[r] = nullptr;
+      g.lda[r] = g.ldb[r] = g.K[r] = 0;
+      g.send[r] = sl;
+    }
+    g.C = w.Q_out + (size_t)r0 * n;
+    g.M = n;
+    g.N = b;
+    g.ldc = n;
+    g.vec = vec && !((uintptr_t)g.C & 15);
+    g.tiles_m = ff_tiles(n);
+    g.nseg = ns;
   }
   if (threadIdx.x == 0) {
     const int tm = ff_tiles(n);
     int a = 0, c = 0;
     for (int I = 0; I < nb; ++I) {
-      for (int d = 0; d < FF_ND; ++d) f.prefix[d * (nb + 1) + I] = d == 1 ? c : a;
+      f.prefix[I] = c;
+      f.prefix[(nb + 1) + I] = a;
       a += tm * ff_tiles(ff_bsize(n, nb, I));
       c += tm * ff_tiles(kp);
     }
-    for (int d = 0; d < FF_ND; ++d) f.prefix[d * (nb + 1) + nb] = d == 1 ? c : a;
+    f.prefix[nb] = c;
+    f.prefix[(nb + 1) + nb] = a;
     f.flags[0] = ok ? 0 : 1;                                             // far path skipped
     f.flags[1] = (ok || __builtin_nontemporal_load(&w.st->status) != 0) ? 1 : 0;  // dense skipped
   }
@@ -326,18 +353,11 @@ hipError_t launch_qw_farfield(const Work& w, const FarField& f, hipStream_t s) {
   // the dense product, used when the plan rejected the far-field path
   e = launch_dgemm(n, n, n, w.Q_in, n, w.W, n, w.Q_out, n, f.flags + 1, s);
   if (e != hipSuccess) return e;
-  e = launch_dgemm_desc(false, f.desc + nb, f.prefix + (nb + 1), nb, p2m, f.flags, s);
+  e = launch_dgemm_desc(false, f.desc, f.prefix, nb, p2m, f.flags, s);
   if (e != hipSuccess) return e;
   e = launch_dgemm(k * n, np, np, f.M, k * n, f.T, np, f.L, k * n, f.flags, s);
   if (e != hipSuccess) return e;
-  e = launch_dgemm_desc(false, f.desc, f.prefix, nb, band, f.flags, s);
-  if (e != hipSuccess) return e;
-  for (int r = 0; r < FF_XR; ++r) {
-    e = launch_dgemm_desc(true, f.desc + (3 + r) * nb, f.prefix + (3 + r) * (nb + 1), nb, band,
-                          f.flags, s);
-    if (e != hipSuccess) return e;
-  }
-  return launch_dgemm_desc(true, f.desc + 2 * nb, f.prefix + 2 * (nb + 1), nb, band, f.flags, s);
+  return launch_dgemm_seg(f.seg, f.prefix + (nb + 1), nb, band, f.flags, s);
 }
 
 }  // namespace eigupd

@@ -44,12 +44,48 @@ __device__ __forceinline__ void tile_of(int bid, int tiles_m, int tiles_n, int* 
 // doubles of the A slice (pairs of rows 32 apart in one k-column) and BT/16 of
 // the B slice (consecutive k of one column of B).  Every tile size runs the
 // same k-slices in the same order, so C is bitwise the same for any BT.
-// ACC: C += A B instead of C = A B.
-template <int BT, bool ACC = false>
-__device__ __forceinline__ void dgemm_tile(int M, int N, int Kd, const double* __restrict__ A,
-                                           int lda, const double* __restrict__ B, int ldb,
-                                           double* __restrict__ C, int ldc, int tm, int tn,
-                                           int vec) {
+// ACC: C += A B instead of C = A B.  Src supplies, for k-slice s, the operands
+// and the slice's offset and extent in them (one matrix pair, or segments of
+// several pairs summed into one C); kg is the slice's offset in the summed k.
+struct PlainSrc {
+  const double* A;
+  const double* B;
+  int lda, ldb, K;
+  __device__ __forceinline__ int slices() const { return (K + GBK - 1) / GBK; }
+  __device__ __forceinline__ void at(int kg, const double* __restrict__& a, int& la,
+                                     const double* __restrict__& b, int& lb,
+                                     int& k0, int& kd) const {
+    a = A;
+    la = lda;
+    b = B;
+    lb = ldb;
+    k0 = kg;
+    kd = K;
+  }
+};
+
+struct SegSrc {
+  const GemmSegDesc& d;
+  __device__ __forceinline__ int slices() const { return d.send[d.nseg - 1]; }
+  __device__ __forceinline__ void at(int kg, const double* __restrict__& a, int& la,
+                                     const double* __restrict__& b, int& lb,
+                                     int& k0, int& kd) const {
+    const int s = kg / GBK;
+    int i = 0;
+    while (i + 1 < d.nseg && s >= d.send[i]) ++i;
+    a = d.A[i];
+    la = d.lda[i];
+    b = d.B[i];
+    lb = d.ldb[i];
+    k0 = (s - (i ? d.send[i - 1] : 0)) * GBK;
+    kd = d.K[i];
+  }
+};
+
+template <int BT, bool ACC, typename Src>
+__device__ __forceinline__ void dgemm_tile_src(int M, int N, const Src& src,
+                                               double* __restrict__ C, int ldc, int tm, int tn,
+                                               int vec) {
   constexpr int WT = BT / 2;          // wave sub-tile
   constexpr int FT = WT / 16;         // MFMA tiles per wave side
   constexpr int AQ = BT / 32;         // A row pairs per thread
@@ -67,7 +103,11 @@ __device__ __forceinline__ void dgemm_tile(int M, int N, int Kd, const double* _
   const bool full_m = vec && (m0 + BT <= M), full_n = vec && (n0 + BT <= N);
   double ra0[2 * AQ], rb0[KPT], ra1[2 * AQ], rb1[KPT];
 
-  auto gload = [&](int k0, double (&ra)[2 * AQ], double (&rb)[KPT]) {
+  auto gload = [&](int kg, double (&ra)[2 * AQ], double (&rb)[KPT]) {
+    const double* __restrict__ A;
+    const double* __restrict__ B;
+    int lda, ldb, k0, Kd;
+    src.at(kg, A, lda, B, ldb, k0, Kd);
     const bool full_k = (k0 + GBK <= Kd);
     const int ka = k0 + a_k;
     if (full_m && full_k) {
@@ -115,7 +155,7 @@ __device__ __forceinline__ void dgemm_tile(int M, int N, int Kd, const double* _
 #pragma unroll
     for (int j = 0; j < FT; ++j) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
 
-  const int nk = (Kd + GBK - 1) / GBK;
+  const int nk = src.slices();
   const int fr = lane & 15, fk = lane >> 4;
   auto compute = [&](int cur) {
 #pragma unroll
@@ -171,6 +211,14 @@ __device__ __forceinline__ void dgemm_tile(int M, int N, int Kd, const double* _
         }
       }
     }
+}
+
+template <int BT, bool ACC = false>
+__device__ __forceinline__ void dgemm_tile(int M, int N, int Kd, const double* __restrict__ A,
+                                           int lda, const double* __restrict__ B, int ldb,
+                                           double* __restrict__ C, int ldc, int tm, int tn,
+                                           int vec) {
+  dgemm_tile_src<BT, ACC>(M, N, PlainSrc{A, B, lda, ldb, Kd}, C, ldc, tm, tn, vec);
 }
 
 __global__ __launch_bounds__(GNT, 2) void dgemm_kernel(int M, int N, int Kd,
@@ -232,6 +280,35 @@ __global__ __launch_bounds__(GNT, 2) void dgemm_desc(const GemmDescG* __restrict
   const int t = b - prefix[lo];
   dgemm_tile<GBM, ACC>(g.M, g.N, g.K, g.A, g.lda, g.B, g.ldb, g.C, g.ldc, t % g.tiles_m,
                        t / g.tiles_m, g.vec);
+}
+
+// Segmented products C = sum_i A_i B_i from device-built descriptors (block b is
+// tile b - prefix[i] of instance i); skipped on the device when *skip != 0.
+__global__ __launch_bounds__(GNT, 2) void dgemm_seg(const GemmSegDesc* __restrict__ d,
+                                                    const int* __restrict__ prefix, int ninst,
+                                                    const int32_t* skip) {
+  if (__builtin_nontemporal_load(skip) != 0) return;
+  int lo = 0, hi = ninst - 1;
+  const int b = blockIdx.x;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (prefix[mid] <= b)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  const GemmSegDesc& g = d[lo];
+  if (g.M <= 0 || g.N <= 0 || g.nseg <= 0) return;
+  const int t = b - prefix[lo];
+  dgemm_tile_src<GBM, false>(g.M, g.N, SegSrc{g}, g.C, g.ldc, t % g.tiles_m, t / g.tiles_m,
+                             g.vec);
+}
+
+hipError_t launch_dgemm_seg(const GemmSegDesc* d, const int* prefix, int ninst, int blocks,
+                            const int32_t* skip, hipStream_t s) {
+  if (blocks <= 0) return hipSuccess;
+  hipLaunchKernelGGL(dgemm_seg, dim3(blocks), dim3(GNT), 0, s, d, prefix, ninst, skip);
+  return hipGetLastError();
 }
 
 hipError_t launch_dgemm_desc(bool acc, const GemmDescG* d, const int* prefix, int ninst,

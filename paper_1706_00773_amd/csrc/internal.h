@@ -176,6 +176,19 @@ struct GemmDescG {
   int M, N, K, lda, ldb, ldc, vec, tiles_m;
 };
 
+// C = sum_i A_i B_i over up to GSEG operand pairs (all M rows, N columns;
+// A_i is M x K_i, B_i is K_i x N, column-major), built on the device; send[i] =
+// k-slices (of 16) of pairs 0..i together; vec: 16-byte accesses allowed for
+// every pair and C.
+constexpr int GSEG = 6;
+struct GemmSegDesc {
+  const double* A[GSEG];
+  const double* B[GSEG];
+  double* C;
+  int lda[GSEG], ldb[GSEG], K[GSEG], send[GSEG];
+  int M, N, ldc, vec, tiles_m, nseg;
+};
+
 // Q' = Q W with the far blocks of W from Chebyshev expansions (farfield.hip):
 // buffers of one state, laid out by ff_layout in ff_bytes(n, k) bytes.
 struct FarField {
@@ -188,8 +201,9 @@ struct FarField {
   double* iv;     // 4 per block: pole interval, column-point interval
   double* xn;     // nb P column-block nodes
   double* yn;     // nb P row-block nodes
-  GemmDescG* desc;  // 7 nb: near band, P2M, L2P, four rounds of extra near pairs
-  int* prefix;    // 7 (nb + 1) tile offsets
+  GemmDescG* desc;    // nb: P2M
+  GemmSegDesc* seg;   // nb: band + extra near pairs + L2P of each column block
+  int* prefix;        // 2 (nb + 1) tile offsets: P2M, segmented products
   int* near;      // 2 nb: first and last row block of each near band
   int* extra;     // 4 nb: row blocks of the extra near pairs of each column block (-1: none)
   int* flags;     // [0] far path skipped, [1] dense path skipped
@@ -226,6 +240,9 @@ hipError_t launch_perturb_w(const Work& w, double* lam_out, hipStream_t s);
 // C = A * B, column-major, FP64 MFMA.  Skipped on the device when *status != 0.
 hipError_t launch_dgemm(int M, int N, int Kd, const double* A, int lda, const double* B, int ldb,
                         double* C, int ldc, const int32_t* status, hipStream_t s);
+// Segmented products from ninst device-built descriptors (tiles as below).
+hipError_t launch_dgemm_seg(const GemmSegDesc* d, const int* prefix, int ninst, int blocks,
+                            const int32_t* skip, hipStream_t s);
 // Products from ninst device-built descriptors (acc: C += A B); block b of the
 // grid is tile b - prefix[i] of instance i; skipped on the device when *skip != 0.
 hipError_t launch_dgemm_desc(bool acc, const GemmDescG* d, const int* prefix, int ninst,
