@@ -131,8 +131,10 @@ enum {
                                their width apart).  Falls back to the dense
                                product on the device when the update merged
                                equal poles; ignored for n < 2048 and with the
-                               reduced-precision modes.  Allocates its buffers
-                               (about 2 k n^2 P / 256 doubles) on first use. */
+                               reduced-precision modes.  Only the blocks of W
+                               it reads are formed (the debug copy of W is then
+                               partial).  Allocates its buffers (about
+                               2 k n^2 P / 256 doubles) on first use. */
 };
 
 enum { EIG_KMAX = 8 };

@@ -348,11 +348,17 @@ int eig_update_rankk(eig_state_t s, int64_t k, const double* K, int64_t ldk, con
   }
   w.lam_fin = w.lam_out;
   HIPCHK(launch_finalize(w, st));
-  HIPCHK(launch_wbuild(w, st));
+  const FarField ff = farfield ? ff_layout(s->ff_block, (int)n, (int)k) : FarField{};
+  if (farfield) {
+    HIPCHK(launch_ff_plan(w, ff, st));
+    HIPCHK(launch_wbuild_ff(w, ff, st));
+  } else {
+    HIPCHK(launch_wbuild(w, st));
+  }
   HIPCHK(launch_group_reflect(w, st));
   HIPCHK(mark(5));
   if (farfield)
-    HIPCHK(launch_qw_farfield(w, ff_layout(s->ff_block, (int)n, (int)k), st));
+    HIPCHK(launch_qw_farfield(w, ff, st));
   else if (prec == EIG_GEMM_FP64)
     HIPCHK(launch_dgemm((int)n, (int)n, (int)n, w.Q_in, (int)n, w.W, (int)n, w.Q_out, (int)n,
                         &w.st->status, st));

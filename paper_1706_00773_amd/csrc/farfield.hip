@@ -336,11 +336,16 @@ __global__ __launch_bounds__(256) void ff_weights_kernel(Work w, FarField f) {
   }
 }
 
+hipError_t launch_ff_plan(const Work& w, const FarField& f, hipStream_t s) {
+  if (f.nb < 1) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(ff_interval_kernel, dim3(f.nb), dim3(256), 0, s, w, f);
+  hipLaunchKernelGGL(ff_plan_kernel, dim3(1), dim3(256), 0, s, w, f);
+  return hipGetLastError();
+}
+
 hipError_t launch_qw_farfield(const Work& w, const FarField& f, hipStream_t s) {
   const int n = w.n, k = w.k, nb = f.nb, kp = k * FF_P, np = nb * FF_P;
   if (nb < 1) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(ff_interval_kernel, dim3(nb), dim3(256), 0, s, w, f);
-  hipLaunchKernelGGL(ff_plan_kernel, dim3(1), dim3(256), 0, s, w, f);
   const long long ne = (long long)np * np;
   hipLaunchKernelGGL(ff_t_kernel, dim3((unsigned)((ne + 255) / 256)), dim3(256), 0, s, f);
   hipLaunchKernelGGL(ff_weights_kernel, dim3((2 * n + 255) / 256), dim3(256), 0, s, w, f);

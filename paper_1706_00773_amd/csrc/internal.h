@@ -212,8 +212,12 @@ bool ff_eligible(int n, int k);
 int ff_blocks(int n);
 size_t ff_bytes(int n, int k);
 FarField ff_layout(void* base, int n, int k);
-// Enqueues the plan, both product paths (one of them exits at once) and leaves
-// Q_out = Q_in W.  Needs finalize and wbuild to have run.
+// The plan (intervals, near bands, path decision); needs finalize to have run.
+hipError_t launch_ff_plan(const Work& w, const FarField& f, hipStream_t s);
+// W on the blocks the far-field product reads (all of W if the plan fell back).
+hipError_t launch_wbuild_ff(const Work& w, const FarField& f, hipStream_t s);
+// Both product paths (one of them exits at once): Q_out = Q_in W.  Needs the
+// plan and W (launch_wbuild_ff, then group reflectors) to have run.
 hipError_t launch_qw_farfield(const Work& w, const FarField& f, hipStream_t s);
 
 // Launchers (stream-ordered, no allocation).

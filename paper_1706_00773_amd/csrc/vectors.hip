@@ -191,6 +191,20 @@ template <int K, int CB>
 __global__ __launch_bounds__(256) void wbuild_kernel(Work w) {
   wbuild_body<K, CB>(w, blockIdx.x, blockIdx.y);
 }
+// Far-field product: only the blocks of W it reads (the near band and the extra
+// near pairs of each column block), all of W when its plan fell back to the
+// dense product.  Row tiles of 256 coincide with its row blocks.
+template <int K, int CB>
+__global__ __launch_bounds__(256) void wbuild_ff_kernel(Work w, FarField f) {
+  if (__builtin_nontemporal_load(&f.flags[0]) == 0) {
+    const int nb = f.nb;
+    const int J = min((int)blockIdx.x, nb - 1), I = min((int)blockIdx.y * CB / 256, nb - 1);
+    bool need = J >= f.near[2 * I] && J <= f.near[2 * I + 1];
+    for (int r = 0; r < GSEG - 2; ++r) need = need || f.extra[I * (GSEG - 2) + r] == J;
+    if (!need) return;
+  }
+  wbuild_body<K, CB>(w, blockIdx.x, blockIdx.y);
+}
 template <int K, int CB>
 __global__ __launch_bounds__(256) void wbuild_group(Group g) {
   const int i = group_instance(g, blockIdx.x);
@@ -233,6 +247,19 @@ static hipError_t wbuild_launch(const Work& w, hipStream_t s) {
   dim3 grid((w.n + 255) / 256, (w.ncols + WB_CB - 1) / WB_CB);
   hipLaunchKernelGGL((wbuild_kernel<K, WB_CB>), grid, dim3(256), 0, s, w);
   return hipGetLastError();
+}
+
+template <int K>
+static hipError_t wbuild_ff_launch(const Work& w, const FarField& f, hipStream_t s) {
+  static_assert(256 % WB_CB == 0, "column groups inside a far-field block");
+  if (w.ncols <= 0) return hipSuccess;
+  dim3 grid((w.n + 255) / 256, (w.ncols + WB_CB - 1) / WB_CB);
+  hipLaunchKernelGGL((wbuild_ff_kernel<K, WB_CB>), grid, dim3(256), 0, s, w, f);
+  return hipGetLastError();
+}
+
+hipError_t launch_wbuild_ff(const Work& w, const FarField& f, hipStream_t s) {
+  EIGUPD_SWITCH_K(w.k, wbuild_ff_launch, w, f, s)
 }
 
 template <int K>
