@@ -42,7 +42,8 @@ constexpr int FF_B = 256;        // rows / columns per block
 constexpr int FF_P = 24;         // Chebyshev nodes per interval
 constexpr double FF_ETA = 0.5;   // far: distance >= FF_ETA * max(width_I, width_J)
 constexpr int FF_MIN_N = 2048;   // below this the dense product is used
-constexpr int FF_TILE = 128;     // tile side of the descriptor products
+constexpr int FF_TILE = 128;     // tile side of the band / L2P products
+constexpr int FF_PTILE = 64;     // tile side of the P2M products (N = kP is small)
 constexpr int FF_XR = GSEG - 2;  // extra near pairs per column block
 
 int ff_blocks(int n) { return n / FF_B; }
@@ -50,6 +51,7 @@ __host__ __device__ static inline int ff_bsize(int n, int nb, int i) {
   return i + 1 < nb ? FF_B : n - (nb - 1) * FF_B;
 }
 __host__ __device__ static inline int ff_tiles(int x) { return (x + FF_TILE - 1) / FF_TILE; }
+__host__ __device__ static inline int ff_ptiles(int x) { return (x + FF_PTILE - 1) / FF_PTILE; }
 
 bool ff_eligible(int n, int k) { return n >= FF_MIN_N && k >= 1 && k <= KMAX; }
 
@@ -177,7 +179,7 @@ __device__ __forceinline__ bool ff_far(const double* iv, int I, int J) {
 }
 
 __device__ __forceinline__ GemmDescG ff_desc(const double* A, int lda, const double* B, int ldb,
-                                             double* C, int ldc, int M, int N, int K) {
+                                             double* C, int ldc, int M, int N, int K, int bt) {
   GemmDescG g;
   g.A = A;
   g.B = B;
@@ -190,7 +192,7 @@ __device__ __forceinline__ GemmDescG ff_desc(const double* A, int lda, const dou
   g.ldc = ldc;
   g.vec = !((lda & 1) || (ldb & 1) || (ldc & 1) || ((uintptr_t)A & 15) || ((uintptr_t)B & 15) ||
             ((uintptr_t)C & 15));
-  g.tiles_m = (M + FF_TILE - 1) / FF_TILE;
+  g.tiles_m = (M + bt - 1) / bt;
   return g;
 }
 
@@ -239,7 +241,7 @@ __global__ __launch_bounds__(256) void ff_plan_kernel(Work w, FarField f) {
     const int k0 = lo * FF_B, kn = (hi + 1 == nb ? n : (hi + 1) * FF_B) - k0;
     // P2M: M_I = Q(:, I) B_I
     f.desc[I] = ff_desc(w.Q_in + (size_t)r0 * n, n, f.B + (size_t)r0 * kp, b,
-                        f.M + (size_t)I * FF_P * k * n, n, n, kp, b);
+                        f.M + (size_t)I * FF_P * k * n, n, n, kp, b, FF_PTILE);
     // Q'(:, I) = Q(:, band) W(band, I) + sum_extra Q(:, J) W(J, I) + L_I Phi_I
     GemmSegDesc& g = f.seg[I];  // written in place
     int ns = 0, sl = 0;
@@ -284,7 +286,7 @@ __global__ __launch_bounds__(256) void ff_plan_kernel(Work w, FarField f) {
       f.prefix[I] = c;
       f.prefix[(nb + 1) + I] = a;
       a += tm * ff_tiles(ff_bsize(n, nb, I));
-      c += tm * ff_tiles(kp);
+      c += ff_ptiles(n) * ff_ptiles(kp);
     }
     f.prefix[nb] = c;
     f.prefix[(nb + 1) + nb] = a;
@@ -354,11 +356,11 @@ hipError_t launch_qw_farfield(const Work& w, const FarField& f, hipStream_t s) {
   const int tm = ff_tiles(n);
   int band = 0;
   for (int I = 0; I < nb; ++I) band += tm * ff_tiles(ff_bsize(n, nb, I));
-  const int p2m = nb * tm * ff_tiles(kp);
+  const int p2m = nb * ff_ptiles(n) * ff_ptiles(kp);
   // the dense product, used when the plan rejected the far-field path
   e = launch_dgemm(n, n, n, w.Q_in, n, w.W, n, w.Q_out, n, f.flags + 1, s);
   if (e != hipSuccess) return e;
-  e = launch_dgemm_desc(false, f.desc, f.prefix, nb, p2m, f.flags, s);
+  e = launch_dgemm_desc(false, FF_PTILE, f.desc, f.prefix, nb, p2m, f.flags, s);
   if (e != hipSuccess) return e;
   e = launch_dgemm(k * n, np, np, f.M, k * n, f.T, np, f.L, k * n, f.flags, s);
   if (e != hipSuccess) return e;

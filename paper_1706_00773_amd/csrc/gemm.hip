@@ -64,26 +64,40 @@ struct PlainSrc {
   }
 };
 
+// Segments are visited in increasing slice order (the tile asks for slices
+// 0, 1, 2, ...), so a cursor loads the next segment's operands only when the
+// slice index crosses a segment end.
 struct SegSrc {
   const GemmSegDesc& d;
+  int i = -1, s0 = 0, s1 = 0;  // current segment and its slices [s0, s1)
+  const double* A = nullptr;
+  const double* B = nullptr;
+  int lda = 0, ldb = 0, K = 0;
   __device__ __forceinline__ int slices() const { return d.send[d.nseg - 1]; }
   __device__ __forceinline__ void at(int kg, const double* __restrict__& a, int& la,
-                                     const double* __restrict__& b, int& lb,
-                                     int& k0, int& kd) const {
+                                     const double* __restrict__& b, int& lb, int& k0, int& kd) {
     const int s = kg / GBK;
-    int i = 0;
-    while (i + 1 < d.nseg && s >= d.send[i]) ++i;
-    a = d.A[i];
-    la = d.lda[i];
-    b = d.B[i];
-    lb = d.ldb[i];
-    k0 = (s - (i ? d.send[i - 1] : 0)) * GBK;
-    kd = d.K[i];
+    while (s >= s1 && i + 1 < d.nseg) {
+      ++i;
+      s0 = s1;
+      s1 = d.send[i];
+      A = d.A[i];
+      B = d.B[i];
+      lda = d.lda[i];
+      ldb = d.ldb[i];
+      K = d.K[i];
+    }
+    a = A;
+    la = lda;
+    b = B;
+    lb = ldb;
+    k0 = (s - s0) * GBK;
+    kd = K;
   }
 };
 
 template <int BT, bool ACC, typename Src>
-__device__ __forceinline__ void dgemm_tile_src(int M, int N, const Src& src,
+__device__ __forceinline__ void dgemm_tile_src(int M, int N, Src src,
                                                double* __restrict__ C, int ldc, int tm, int tn,
                                                int vec) {
   constexpr int WT = BT / 2;          // wave sub-tile
@@ -261,7 +275,7 @@ __global__ __launch_bounds__(GNT, 2) void dgemm_group(const GemmDesc* __restrict
 // Products of general shapes from device-built descriptors: block b is tile
 // b - prefix[i] of instance i, tiles ordered down the columns of C.  Skipped on
 // the device when *skip != 0.
-template <bool ACC>
+template <bool ACC, int BT>
 __global__ __launch_bounds__(GNT, 2) void dgemm_desc(const GemmDescG* __restrict__ d,
                                                      const int* __restrict__ prefix, int ninst,
                                                      const int32_t* skip) {
@@ -278,8 +292,8 @@ __global__ __launch_bounds__(GNT, 2) void dgemm_desc(const GemmDescG* __restrict
   const GemmDescG& g = d[lo];
   if (g.M <= 0 || g.N <= 0 || g.K <= 0) return;  // an empty instance
   const int t = b - prefix[lo];
-  dgemm_tile<GBM, ACC>(g.M, g.N, g.K, g.A, g.lda, g.B, g.ldb, g.C, g.ldc, t % g.tiles_m,
-                       t / g.tiles_m, g.vec);
+  dgemm_tile<BT, ACC>(g.M, g.N, g.K, g.A, g.lda, g.B, g.ldb, g.C, g.ldc, t % g.tiles_m,
+                      t / g.tiles_m, g.vec);
 }
 
 // Segmented products C = sum_i A_i B_i from device-built descriptors (block b is
@@ -311,13 +325,20 @@ hipError_t launch_dgemm_seg(const GemmSegDesc* d, const int* prefix, int ninst, 
   return hipGetLastError();
 }
 
-hipError_t launch_dgemm_desc(bool acc, const GemmDescG* d, const int* prefix, int ninst,
+hipError_t launch_dgemm_desc(bool acc, int bt, const GemmDescG* d, const int* prefix, int ninst,
                              int blocks, const int32_t* skip, hipStream_t s) {
   if (blocks <= 0) return hipSuccess;
-  if (acc)
-    hipLaunchKernelGGL((dgemm_desc<true>), dim3(blocks), dim3(GNT), 0, s, d, prefix, ninst, skip);
+  if (bt == 128 && acc)
+    hipLaunchKernelGGL((dgemm_desc<true, 128>), dim3(blocks), dim3(GNT), 0, s, d, prefix, ninst,
+                       skip);
+  else if (bt == 128)
+    hipLaunchKernelGGL((dgemm_desc<false, 128>), dim3(blocks), dim3(GNT), 0, s, d, prefix, ninst,
+                       skip);
+  else if (bt == 64 && !acc)
+    hipLaunchKernelGGL((dgemm_desc<false, 64>), dim3(blocks), dim3(GNT), 0, s, d, prefix, ninst,
+                       skip);
   else
-    hipLaunchKernelGGL((dgemm_desc<false>), dim3(blocks), dim3(GNT), 0, s, d, prefix, ninst, skip);
+    return hipErrorInvalidValue;
   return hipGetLastError();
 }
 

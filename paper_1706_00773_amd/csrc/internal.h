@@ -168,7 +168,7 @@ struct GemmDesc {
 };
 
 // One product C (+)= A B of a general shape, column-major, built on the device;
-// tiles_m = ceil(M / 128); vec: 16-byte accesses allowed.
+// tiles_m = ceil(M / tile side); vec: 16-byte accesses allowed.
 struct GemmDescG {
   const double* A;
   const double* B;
@@ -247,9 +247,10 @@ hipError_t launch_dgemm(int M, int N, int Kd, const double* A, int lda, const do
 // Segmented products from ninst device-built descriptors (tiles as below).
 hipError_t launch_dgemm_seg(const GemmSegDesc* d, const int* prefix, int ninst, int blocks,
                             const int32_t* skip, hipStream_t s);
-// Products from ninst device-built descriptors (acc: C += A B); block b of the
-// grid is tile b - prefix[i] of instance i; skipped on the device when *skip != 0.
-hipError_t launch_dgemm_desc(bool acc, const GemmDescG* d, const int* prefix, int ninst,
+// Products from ninst device-built descriptors (acc: C += A B) on bt x bt tiles
+// (128, or 64 without acc; tiles_m = ceil(M / bt)); block b of the grid is tile
+// b - prefix[i] of instance i; skipped on the device when *skip != 0.
+hipError_t launch_dgemm_desc(bool acc, int bt, const GemmDescG* d, const int* prefix, int ninst,
                              int blocks, const int32_t* skip, hipStream_t s);
 // Grouped launches over `ninst` instances of one rank k (blocks = total blocks,
 // Group.prefix built from the per-instance counts below).
