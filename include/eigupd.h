@@ -131,7 +131,9 @@ enum {
                                their width apart).  Falls back to the dense
                                product on the device when the update merged
                                equal poles; ignored for n < 2048 and with the
-                               reduced-precision modes.  Only the blocks of W
+                               reduced-precision modes; single updates only
+                               (eig_update_batch returns EIG_EUNSUPPORTED for
+                               it).  Only the blocks of W
                                it reads are formed (the debug copy of W is then
                                partial).  Allocates its buffers (about
                                2 k n^2 P / 256 doubles) on first use. */

@@ -329,6 +329,11 @@ enum { PH_FIRST = 0, PH_SOLVE = 1, PH_DONE = 2 };
 // summed into its diagonal.
 constexpr double STAG = 1e-9;
 constexpr double NOISE_C = 64.0;
+// Newton in its quadratic phase: a step at most QUAD_R times the previous one.
+// Then the next step is about r^2 times this one (r the ratio of the two), and
+// when that is below the rounding level of tau the Newton point is taken
+// without another evaluation.
+constexpr double QUAD_R = 1e-3;
 
 // Launch shape of the root solver: RPB root slots per block, each slot's pole
 // sums split over WV waves x SPLIT parts of a wave.  A slot whose root has
@@ -570,7 +575,10 @@ __device__ __forceinline__ void rootsolve_body(const Work& w) {
           // halving while its step is small, or while S is singular to within the
           // rounding error of its sums (the noise floor of the evaluation)
           const bool stalled = ad > 0.5 * fabs(z.dprev);
-          if (ad <= 4.0 * EPSU * fabs(tn) || (stalled && ad <= STAG * fabs(tn)) ||
+          const double r = ad / fabs(z.dprev);
+          const bool quad = z.last_newton && r <= QUAD_R && r * r * ad <= 4.0 * EPSU * fabs(tn) &&
+                            tn > z.tlo && tn < z.thi;
+          if (ad <= 4.0 * EPSU * fabs(tn) || quad || (stalled && ad <= STAG * fabs(tn)) ||
               (stalled && thmin <= NOISE_C * EPSU * err)) {
             conv = true;
             next = fmin(fmax(tn, z.tlo), z.thi);

@@ -74,6 +74,8 @@ def test_farfield_matches_dense_and_oracle(name, make):
     u = make()
     ld, Qd, lf, Qf, info = _both(u)
     assert np.array_equal(ld, lf)
+    # the far-field path ran (its fallback, the dense product, is bitwise Qd)
+    assert not np.array_equal(Qf, Qd)
     assert np.abs(Qf - Qd).max() <= DIFF_TOL
     _check_oracle(u, lf, Qf)
 
@@ -97,6 +99,7 @@ def test_farfield_chained_updates():
             s.query(lo, Qo)
             outs.append((lo.cpu().numpy(), Qo.cpu().numpy()))
     (ld, Qd), (lf, Qf) = outs
+    assert not np.array_equal(Qf, Qd)  # the far-field path ran
     assert np.abs(lf - ld).max() <= 1e-13 * np.abs(ld).max()
     assert np.abs(Qf - Qd).max() <= DIFF_TOL
     assert np.abs(Qf.T @ Qf - np.eye(n)).max() <= ORTH_TOL
@@ -167,6 +170,7 @@ def test_headline_size_n8192():
             outs.append((lo, Qo))
     (ld, Qd), (lf, Qf) = outs
     assert torch.equal(ld, lf)
+    assert not torch.equal(Qf, Qd)  # the far-field path ran
     assert float((Qf - Qd).abs().max()) <= DIFF_TOL
     cols = np.random.default_rng(45).choice(n, 256, replace=False)
     Qs = Qf[:, cols].cpu().numpy()
