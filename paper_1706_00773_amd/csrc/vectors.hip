@@ -45,16 +45,12 @@ __device__ __forceinline__ int count_less_equal(const double* v, int n, double x
 // Merges the roots [r_lo, r_hi) of the reduced problem (made monotone by a
 // running maximum) with the deflated eigenvalues [e_lo, e_hi) (all of them for
 // a full update) into lam_fin[0 ..) and one ColParam per output column.
-template <int K>
-__device__ __forceinline__ void finalize_body(const Work& w) {
-  double* lam_dst = w.lam_fin;
+// Running maximum of the absolute roots into xs (one block).
+__device__ __forceinline__ void finalize_scan_body(const Work& w) {
   __shared__ double s_carry;
   __shared__ double shd[FNT / 64];
   if (update_cancelled(w.st)) return;
   const int r_lo = w.info->r_lo, r_hi = w.info->r_hi;
-  const int e_lo = w.info->e_lo, e_hi = w.info->e_hi;
-  const double* dval = w.dval + e_lo;
-  const int n_e = e_hi - e_lo, n_r = r_hi - r_lo;
   if (threadIdx.x == 0) s_carry = -INFINITY;
   __syncthreads();
   // absolute root values, running maximum
@@ -75,8 +71,19 @@ __device__ __forceinline__ void finalize_body(const Work& w) {
     if (threadIdx.x == FNT - 1) s_carry = v;
     __syncthreads();
   }
-  __syncthreads();
-  for (int i = r_lo + threadIdx.x; i < r_hi; i += FNT) {
+}
+
+// Output columns: merged eigenvalues and one ColParam each (threads t0, t0 +
+// stride, ... of the roots and of the deflated eigenvalues); needs xs.
+template <int K>
+__device__ __forceinline__ void finalize_cols_body(const Work& w, int t0, int stride) {
+  double* lam_dst = w.lam_fin;
+  if (update_cancelled(w.st)) return;
+  const int r_lo = w.info->r_lo, r_hi = w.info->r_hi;
+  const int e_lo = w.info->e_lo, e_hi = w.info->e_hi;
+  const double* dval = w.dval + e_lo;
+  const int n_e = e_hi - e_lo, n_r = r_hi - r_lo;
+  for (int i = r_lo + t0; i < r_hi; i += stride) {
     const double x = w.xs[i];
     const int pos = (i - r_lo) + count_less(dval, n_e, x);
     lam_dst[pos] = x;
@@ -95,7 +102,7 @@ __device__ __forceinline__ void finalize_body(const Work& w) {
     cp.pad = 0;
     w.colp[pos] = cp;
   }
-  for (int j = threadIdx.x; j < n_e; j += FNT) {
+  for (int j = t0; j < n_e; j += stride) {
     const double v = dval[j];
     const int pos = j + count_less_equal(w.xs + r_lo, n_r, v);
     lam_dst[pos] = v;
@@ -108,6 +115,13 @@ __device__ __forceinline__ void finalize_body(const Work& w) {
     cp.pad = 0;
     w.colp[pos] = cp;
   }
+}
+
+template <int K>
+__device__ __forceinline__ void finalize_body(const Work& w) {
+  finalize_scan_body(w);
+  __syncthreads();
+  finalize_cols_body<K>(w, threadIdx.x, FNT);
 }
 
 // W tile: 256 rows x CB columns per block (block coordinates bx, by).
@@ -233,9 +247,18 @@ __global__ void zero_ints_kernel(int* p, int count) {
 int wbuild_blocks(int n) { return ((n + 255) / 256) * ((n + WB_CB - 1) / WB_CB); }
 int reflect_blocks(int n) { return (n + 3) / 4; }
 
+__global__ __launch_bounds__(FNT) void finalize_scan_kernel(Work w) { finalize_scan_body(w); }
+template <int K>
+__global__ __launch_bounds__(256) void finalize_cols_kernel(Work w) {
+  finalize_cols_body<K>(w, blockIdx.x * 256 + threadIdx.x, gridDim.x * 256);
+}
+
+// A single update: the scan in one block, the columns over the whole GPU (the
+// same arithmetic as the one-block finalize of the grouped launches).
 template <int K>
 static hipError_t finalize_launch(const Work& w, hipStream_t s) {
-  hipLaunchKernelGGL((finalize_kernel<K>), dim3(1), dim3(FNT), 0, s, w);
+  hipLaunchKernelGGL(finalize_scan_kernel, dim3(1), dim3(FNT), 0, s, w);
+  hipLaunchKernelGGL((finalize_cols_kernel<K>), dim3((w.n + 255) / 256), dim3(256), 0, s, w);
   return hipGetLastError();
 }
 
