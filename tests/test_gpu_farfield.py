@@ -61,6 +61,7 @@ def _check_oracle(u, lo, Qo):
 CASES = [
     ("rank2 e_j a^T + a e_j^T, n=2048", lambda: wl.plain_rank2(2048, seed=31, min_gap=1e-12)),
     ("ragged n=2500 (last block 452), k=3", lambda: wl.random_small(2500, 3, seed=32)),
+    ("odd n=2049 (no 16-byte accesses), k=2", lambda: wl.random_small(2049, 2, seed=37)),
     ("k=1, n=2304", lambda: wl.general_rankk(1, n=2304, seed=33)),
     ("k=5, n=2304", lambda: wl.general_rankk(5, n=2304, seed=34)),
     ("k=8, n=2048", lambda: wl.general_rankk(8, n=2048, seed=35)),
