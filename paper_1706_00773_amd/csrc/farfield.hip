@@ -31,9 +31,9 @@
 //
 // The plan (intervals, near bands, descriptors) is made on the device, so the
 // host does not wait.  When the update has merged equal-pole groups (W rows mixed
-// by reflectors), a degenerate interval, or an error, the plan switches the
-// product back to the dense kernel: of the two paths launched, each exits at
-// once unless it was chosen.
+// by reflectors), a degenerate interval, half or more of the column blocks over
+// all rows, or an error, the plan switches the product back to the dense kernel:
+// of the two paths launched, each exits at once unless it was chosen.
 #include "common.h"
 
 namespace eigupd {
@@ -199,10 +199,12 @@ __device__ __forceinline__ GemmDescG ff_desc(const double* A, int lda, const dou
 // One block: near bands and extra pairs, the path decision, nodes, descriptors
 // and prefixes.
 __global__ __launch_bounds__(256) void ff_plan_kernel(Work w, FarField f) {
-  __shared__ int s_ok;
+  __shared__ int s_ok, s_full;
   const int n = w.n, k = w.k, nb = f.nb, kp = k * FF_P;
-  if (threadIdx.x == 0)
+  if (threadIdx.x == 0) {
     s_ok = (__builtin_nontemporal_load(&w.st->status) == 0) && (w.info->n_groups == 0);
+    s_full = 0;
+  }
   __syncthreads();
   for (int I = threadIdx.x; I < nb; I += 256) {
     const double* iv = f.iv + 4 * I;
@@ -226,9 +228,13 @@ __global__ __launch_bounds__(256) void ff_plan_kernel(Work w, FarField f) {
       cnt = 0;
       f.near[2 * I] = 0;
       f.near[2 * I + 1] = nb - 1;
+      atomicAdd(&s_full, 1);
     }
     for (int r = cnt; r < FF_XR; ++r) f.extra[I * FF_XR + r] = -1;
   }
+  __syncthreads();
+  // half or more of the column blocks over all rows: the dense product is cheaper
+  if (threadIdx.x == 0 && 2 * s_full >= nb) s_ok = 0;
   __syncthreads();
   const bool ok = s_ok != 0;
   for (int I = threadIdx.x; I < nb; I += 256) {
