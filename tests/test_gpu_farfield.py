@@ -150,20 +150,28 @@ def test_values_only_and_reduced_precision_ignore_the_mode():
     assert np.array_equal(l32, l32f) and np.array_equal(Q32, Q32f)
 
 
-def test_headline_size_n8192():
-    """n = 8192, k = 2 in the benchmark's workload: entrywise against the dense
-    product, and residual and orthogonality against A' on 256 sampled columns."""
+FULL = [
+    ("rank-2 e_j a^T + a e_j^T, n=8192", lambda dev: wl.headline(8192, device=dev)),
+    ("rank 4, n=8192", lambda dev: wl.general_rankk(4, n=8192, device=dev)),
+    ("rank 8, n=8192", lambda dev: wl.general_rankk(8, n=8192, device=dev)),
+]
+
+
+@pytest.mark.parametrize("name,make", FULL, ids=[c[0] for c in FULL])
+def test_full_size_n8192(name, make):
+    """n = 8192 in the benchmark's workloads: entrywise against the dense product,
+    and residual and orthogonality against A' on 256 sampled columns."""
     import torch
 
-    print("case farfield headline n=8192", flush=True)
+    print(f"case farfield {name}", flush=True)
     n, dev = 8192, "cuda:0"
-    u = wl.headline(n, device=dev)
+    u = make(dev)
+    Kh = u.K.cpu().numpy() if isinstance(u.K, torch.Tensor) else np.asarray(u.K)
     outs = []
     for mode in (0, FF):
         with eu.EigState(n, 0) as s:
             s.upload(torch.as_tensor(np.asarray(u.lam), device=dev), u.Q)
-            s.update(colmajor(np.asarray(u.K.cpu() if isinstance(u.K, torch.Tensor) else u.K), dev),
-                     u.sigma, mode)
+            s.update(colmajor(Kh, dev), u.sigma, mode)
             lo = torch.empty(n, dtype=torch.float64, device=dev)
             Qo = torch.empty((n, n), dtype=torch.float64, device=dev).t()
             s.query(lo, Qo)
@@ -175,7 +183,6 @@ def test_headline_size_n8192():
     cols = np.random.default_rng(45).choice(n, 256, replace=False)
     Qs = Qf[:, cols].cpu().numpy()
     Qh = u.Q.cpu().numpy() if isinstance(u.Q, torch.Tensor) else np.asarray(u.Q)
-    Kh = u.K.cpu().numpy() if isinstance(u.K, torch.Tensor) else np.asarray(u.K)
     lam = np.asarray(u.lam.cpu() if isinstance(u.lam, torch.Tensor) else u.lam)
     lv = lf.cpu().numpy()[cols]
     Aq = Qh @ (lam[:, None] * (Qh.T @ Qs)) + Kh @ (np.asarray(u.sigma, float)[:, None] * (Kh.T @ Qs))
