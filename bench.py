@@ -584,7 +584,7 @@ def measured_traffic(path_name, sources):
 
 
 # Block size and Chebyshev nodes of the library's far-field product (farfield.hip).
-FF_B, FF_P = 256, 20
+FF_B, FF_P = 256, 24
 
 
 def farfield_flops(n, k):

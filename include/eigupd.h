@@ -123,12 +123,12 @@ enum {
   EIG_QW_FARFIELD = 1 << 9  /* FP64, n >= 2048: form Q' = Q W with the far blocks
                                of W (Sec. 2.4, eq. (10)) replaced by Chebyshev
                                expansions of 1/(x - y) (blocks of 256 rows and
-                               columns, 20 nodes per interval): a band of exact
+                               columns, 24 nodes per interval): a band of exact
                                block products plus three small products, about
                                8x fewer flops at n = 8192.  Q' agrees with the
-                               dense product to about 1e-15 (the interpolation
-                               error for blocks at least half their width
-                               apart).  Falls back to the dense
+                               dense product to rounding level (the interpolation
+                               error is below 1e-15 for blocks at least half
+                               their width apart).  Falls back to the dense
                                product on the device when the update merged
                                equal poles; ignored for n < 2048 and with the
                                reduced-precision modes; single updates only

@@ -39,7 +39,7 @@
 namespace eigupd {
 
 constexpr int FF_B = 256;        // rows / columns per block
-constexpr int FF_P = 20;         // Chebyshev nodes per interval
+constexpr int FF_P = 24;         // Chebyshev nodes per interval
 constexpr double FF_ETA = 0.5;   // far: distance >= FF_ETA * max(width_I, width_J)
 constexpr int FF_MIN_N = 2048;   // below this the dense product is used
 constexpr int FF_TILE = 128;     // tile side of the band / L2P products
