@@ -130,7 +130,8 @@ enum {
                                error is below 1e-15 for blocks at least half
                                their width apart).  Falls back to the dense
                                product on the device when the update merged
-                               equal poles; ignored for n < 2048 and with the
+                               equal poles; ignored for n < 2048, for
+                               n >= 2049 * 256 and with the
                                reduced-precision modes; single updates only
                                (eig_update_batch returns EIG_EUNSUPPORTED for
                                it).  Only the blocks of W

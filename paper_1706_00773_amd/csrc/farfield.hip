@@ -44,6 +44,7 @@ constexpr double FF_ETA = 0.5;   // far: distance >= FF_ETA * max(width_I, width
 constexpr int FF_MIN_N = 2048;   // below this the dense product is used
 constexpr int FF_TILE = 128;     // tile side of the band / L2P products
 constexpr int FF_PTILE = 64;     // tile side of the P2M products (N = kP is small)
+constexpr int FF_MAXNB = 2048;   // blocks the plan handles (n up to 2^19)
 constexpr int FF_XR = GSEG - 2;  // extra near pairs per column block
 
 int ff_blocks(int n) { return n / FF_B; }
@@ -53,7 +54,9 @@ __host__ __device__ static inline int ff_bsize(int n, int nb, int i) {
 __host__ __device__ static inline int ff_tiles(int x) { return (x + FF_TILE - 1) / FF_TILE; }
 __host__ __device__ static inline int ff_ptiles(int x) { return (x + FF_PTILE - 1) / FF_PTILE; }
 
-bool ff_eligible(int n, int k) { return n >= FF_MIN_N && k >= 1 && k <= KMAX; }
+bool ff_eligible(int n, int k) {
+  return n >= FF_MIN_N && ff_blocks(n) <= FF_MAXNB && k >= 1 && k <= KMAX;
+}
 
 size_t ff_bytes(int n, int k) {
   const size_t nb = (size_t)ff_blocks(n), np = nb * FF_P, kp = (size_t)k * FF_P;
@@ -199,12 +202,15 @@ __device__ __forceinline__ GemmDescG ff_desc(const double* A, int lda, const dou
 // One block: near bands and extra pairs, the path decision, nodes, descriptors
 // and prefixes.
 __global__ __launch_bounds__(256) void ff_plan_kernel(Work w, FarField f) {
-  __shared__ int s_ok, s_full;
+  __shared__ int s_ok, s_full, s_cnt[FF_XR + 2];
+  __shared__ unsigned char s_key[FF_MAXNB];  // segments beyond the band, per column block
+  __shared__ short s_inv[FF_MAXNB];          // column block of each launch position
   const int n = w.n, k = w.k, nb = f.nb, kp = k * FF_P;
   if (threadIdx.x == 0) {
     s_ok = (__builtin_nontemporal_load(&w.st->status) == 0) && (w.info->n_groups == 0);
     s_full = 0;
   }
+  if (threadIdx.x < FF_XR + 2) s_cnt[threadIdx.x] = 0;
   __syncthreads();
   for (int I = threadIdx.x; I < nb; I += 256) {
     const double* iv = f.iv + 4 * I;
@@ -224,13 +230,17 @@ __global__ __launch_bounds__(256) void ff_plan_kernel(Work w, FarField f) {
           if (cnt < FF_XR) f.extra[I * FF_XR + cnt] = J;
           ++cnt;
         }
+    int key = cnt;      // segments beyond the band (all rows: more than any)
     if (cnt > FF_XR) {  // this column block is multiplied exactly over all rows
       cnt = 0;
+      key = FF_XR + 1;
       f.near[2 * I] = 0;
       f.near[2 * I + 1] = nb - 1;
       atomicAdd(&s_full, 1);
     }
     for (int r = cnt; r < FF_XR; ++r) f.extra[I * FF_XR + r] = -1;
+    s_key[I] = (unsigned char)key;
+    atomicAdd(&s_cnt[key], 1);
   }
   __syncthreads();
   // half or more of the column blocks over all rows: the dense product is cheaper
@@ -249,7 +259,15 @@ __global__ __launch_bounds__(256) void ff_plan_kernel(Work w, FarField f) {
     f.desc[I] = ff_desc(w.Q_in + (size_t)r0 * n, n, f.B + (size_t)r0 * kp, b,
                         f.M + (size_t)I * FF_P * k * n, n, n, kp, b, FF_PTILE);
     // Q'(:, I) = Q(:, band) W(band, I) + sum_extra Q(:, J) W(J, I) + L_I Phi_I
-    GemmSegDesc& g = f.seg[I];  // written in place
+    // Launch order of the column blocks' products: longer ones (more segments)
+    // first, so that their tiles do not run last, alone, after the short ones
+    // (stable in I; the tiles compute the same in any order).
+    const int key = s_key[I];
+    int pos = 0;
+    for (int q = key + 1; q < FF_XR + 2; ++q) pos += s_cnt[q];
+    for (int J = 0; J < I; ++J) pos += (s_key[J] == key) ? 1 : 0;
+    s_inv[pos] = (short)I;
+    GemmSegDesc& g = f.seg[pos];  // written in place
     int ns = 0, sl = 0;
     bool vec = !(n & 1) && !(kp & 1);
     auto add = [&](const double* A, const double* B, int ldb, int K) {
@@ -285,13 +303,14 @@ __global__ __launch_bounds__(256) void ff_plan_kernel(Work w, FarField f) {
     g.tiles_m = ff_tiles(n);
     g.nseg = ns;
   }
+  __syncthreads();
   if (threadIdx.x == 0) {
     const int tm = ff_tiles(n);
     int a = 0, c = 0;
     for (int I = 0; I < nb; ++I) {
       f.prefix[I] = c;
-      f.prefix[(nb + 1) + I] = a;
-      a += tm * ff_tiles(ff_bsize(n, nb, I));
+      f.prefix[(nb + 1) + I] = a;  // the I-th product launched
+      a += tm * ff_tiles(ff_bsize(n, nb, s_inv[I]));
       c += ff_ptiles(n) * ff_ptiles(kp);
     }
     f.prefix[nb] = c;
