@@ -107,6 +107,39 @@ def test_farfield_chained_updates():
     assert np.abs(Qf.T @ Qf - np.eye(n)).max() <= ORTH_TOL
 
 
+def test_nonfinite_perturbation_fails_and_keeps_the_state():
+    """A NaN in K fails the update on the device in the far-field mode as in the
+    dense one: both products are skipped, the state keeps the last committed
+    decomposition, and the next update is a no-op until the error is read."""
+    import torch
+
+    print("case farfield non-finite K n=2048", flush=True)
+    n, dev = 2048, "cuda:0"
+    u = wl.random_small(n, 2, seed=46)
+    bad = np.array(u.K)
+    bad[5, 1] = np.nan
+    outs = []
+    for mode in (0, FF):
+        with eu.EigState(n, 0) as s:
+            s.upload(torch.as_tensor(u.lam, device=dev), colmajor(u.Q, dev))
+            s.update(colmajor(u.K, dev), u.sigma, mode)    # committed
+            s.update(colmajor(bad, dev), u.sigma, mode)    # fails on the device
+            s.update(colmajor(u.K, dev), u.sigma, mode)    # no-op after the failure
+            lo = torch.empty(n, dtype=torch.float64, device=dev)
+            Qo = torch.empty((n, n), dtype=torch.float64, device=dev).t()
+            with pytest.raises(eu.EigError) as e:
+                s.query(lo, Qo)
+            assert e.value.code == eu.EIG_ENONFINITE
+            info = s.query(lo, Qo)                         # error cleared
+            assert info.generation == 1
+            outs.append((lo.cpu().numpy(), Qo.cpu().numpy()))
+    (ld, Qd), (lf, Qf) = outs
+    assert np.array_equal(ld, lf)
+    assert not np.array_equal(Qf, Qd)  # the committed update took the far-field path
+    assert np.abs(Qf - Qd).max() <= DIFF_TOL
+    _check_oracle(u, lf, Qf)
+
+
 def test_equal_poles_fall_back_to_the_dense_product():
     print("case farfield fallback with equal-pole groups n=2048", flush=True)
     n, k = 2048, 2
