@@ -110,23 +110,27 @@ FarField ff_layout(void* base, int n, int k) {
   return f;
 }
 
-// Chebyshev node m of FF_P on [lo, hi] and its barycentric weight.
-__device__ __forceinline__ double ff_node(double lo, double hi, int m) {
-  return 0.5 * (lo + hi) + 0.5 * (hi - lo) * cos((2 * m + 1) * M_PI / (2.0 * FF_P));
+// Chebyshev node m of FF_P on [lo, hi] (c = ff_cos(m)) and its barycentric
+// weight.
+__device__ __forceinline__ double ff_cos(int m) { return cos((2 * m + 1) * M_PI / (2.0 * FF_P)); }
+__device__ __forceinline__ double ff_node(double lo, double hi, double c) {
+  return 0.5 * (lo + hi) + 0.5 * (hi - lo) * c;
 }
 __device__ __forceinline__ double ff_bw(int m) {
   const double s = sin((2 * m + 1) * M_PI / (2.0 * FF_P));
   return (m & 1) ? -s : s;
 }
 
-// Lagrange basis S_m(y), m < FF_P, of the nodes nd (second barycentric form).
-__device__ __forceinline__ void ff_basis(const double* nd, double y, double* S) {
+// Lagrange basis S_m(y), m < FF_P, of the nodes nd (second barycentric form;
+// bw: the weights ff_bw).
+__device__ __forceinline__ void ff_basis(const double* nd, const double* bw, double y,
+                                         double* S) {
   int hit = -1;
   double sum = 0.0;
   for (int m = 0; m < FF_P; ++m) {
     const double dy = y - nd[m];
     if (dy == 0.0) hit = m;
-    S[m] = ff_bw(m) / (dy == 0.0 ? 1.0 : dy);
+    S[m] = bw[m] / (dy == 0.0 ? 1.0 : dy);
     sum += S[m];
   }
   if (hit >= 0) {
@@ -205,12 +209,14 @@ __global__ __launch_bounds__(256) void ff_plan_kernel(Work w, FarField f) {
   __shared__ int s_ok, s_full, s_cnt[FF_XR + 2];
   __shared__ unsigned char s_key[FF_MAXNB];  // segments beyond the band, per column block
   __shared__ short s_inv[FF_MAXNB];          // column block of each launch position
+  __shared__ double s_c[FF_P];
   const int n = w.n, k = w.k, nb = f.nb, kp = k * FF_P;
   if (threadIdx.x == 0) {
     s_ok = (__builtin_nontemporal_load(&w.st->status) == 0) && (w.info->n_groups == 0);
     s_full = 0;
   }
   if (threadIdx.x < FF_XR + 2) s_cnt[threadIdx.x] = 0;
+  if (threadIdx.x < FF_P) s_c[threadIdx.x] = ff_cos(threadIdx.x);
   __syncthreads();
   for (int I = threadIdx.x; I < nb; I += 256) {
     const double* iv = f.iv + 4 * I;
@@ -247,13 +253,15 @@ __global__ __launch_bounds__(256) void ff_plan_kernel(Work w, FarField f) {
   if (threadIdx.x == 0 && 2 * s_full >= nb) s_ok = 0;
   __syncthreads();
   const bool ok = s_ok != 0;
+  for (int e = threadIdx.x; e < nb * FF_P; e += 256) {
+    const double* iv = f.iv + 4 * (e / FF_P);
+    const double c = s_c[e % FF_P];
+    f.yn[e] = ok ? ff_node(iv[0], iv[1], c) : 0.0;
+    f.xn[e] = ok ? ff_node(iv[2], iv[3], c) : 0.0;
+  }
   for (int I = threadIdx.x; I < nb; I += 256) {
     const int lo = f.near[2 * I], hi = f.near[2 * I + 1];
     const int b = ff_bsize(n, nb, I), r0 = I * FF_B;
-    for (int m = 0; m < FF_P; ++m) {
-      f.yn[I * FF_P + m] = ok ? ff_node(f.iv[4 * I], f.iv[4 * I + 1], m) : 0.0;
-      f.xn[I * FF_P + m] = ok ? ff_node(f.iv[4 * I + 2], f.iv[4 * I + 3], m) : 0.0;
-    }
     const int k0 = lo * FF_B, kn = (hi + 1 == nb ? n : (hi + 1) * FF_B) - k0;
     // P2M: M_I = Q(:, I) B_I
     f.desc[I] = ff_desc(w.Q_in + (size_t)r0 * n, n, f.B + (size_t)r0 * kp, b,
@@ -337,15 +345,18 @@ __global__ __launch_bounds__(256) void ff_t_kernel(FarField f) {
 // S_{I,l}(x_p) c_{p,a} (zero for deflated columns).  Threads 0..n-1 take rows,
 // n..2n-1 columns.
 __global__ __launch_bounds__(256) void ff_weights_kernel(Work w, FarField f) {
+  __shared__ double s_bw[FF_P];
   if (__builtin_nontemporal_load(&f.flags[0]) != 0) return;
   const int n = w.n, k = w.k, nb = f.nb, kp = k * FF_P;
   const int t = blockIdx.x * 256 + threadIdx.x;
+  if (threadIdx.x < FF_P) s_bw[threadIdx.x] = ff_bw(threadIdx.x);
+  __syncthreads();
   if (t >= 2 * n) return;
   double S[FF_P];
   if (t < n) {
     const int r = t, J = min(r / FF_B, nb - 1), j = r - J * FF_B, b = ff_bsize(n, nb, J);
     const int jr = w.rmap[r];
-    ff_basis(f.yn + J * FF_P, w.lam_in[r], S);
+    ff_basis(f.yn + J * FF_P, s_bw, w.lam_in[r], S);
     double* Bj = f.B + (size_t)J * FF_B * kp;
     for (int a = 0; a < k; ++a) {
       const double u = jr >= 0 ? w.ru[(size_t)jr * k + a] : 0.0;
@@ -354,7 +365,7 @@ __global__ __launch_bounds__(256) void ff_weights_kernel(Work w, FarField f) {
   } else {
     const int p = t - n, I = min(p / FF_B, nb - 1);
     const ColParam& cp = w.colp[p];
-    ff_basis(f.xn + I * FF_P, ff_colx(w, p), S);
+    ff_basis(f.xn + I * FF_P, s_bw, ff_colx(w, p), S);
     double* ph = f.Phi + (size_t)p * kp;
     for (int a = 0; a < k; ++a) {
       const double c = cp.drow >= 0 ? 0.0 : cp.c[a];

@@ -47,29 +47,46 @@ __device__ __forceinline__ int count_less_equal(const double* v, int n, double x
 // a full update) into lam_fin[0 ..) and one ColParam per output column.
 // Running maximum of the absolute roots into xs (one block).
 __device__ __forceinline__ void finalize_scan_body(const Work& w) {
-  __shared__ double s_carry;
   __shared__ double shd[FNT / 64];
   if (update_cancelled(w.st)) return;
   const int r_lo = w.info->r_lo, r_hi = w.info->r_hi;
-  if (threadIdx.x == 0) s_carry = -INFINITY;
+  // absolute root values, running maximum: each thread takes one run of
+  // consecutive roots, the runs' maxima are scanned across the block, then each
+  // run is written.  Runs of up to FRUN roots are held in registers, their
+  // loads issued together.
+  constexpr int FRUN = 16;
+  const int per = (r_hi - r_lo + FNT - 1) / FNT;
+  const int b0 = min(r_hi, r_lo + (int)threadIdx.x * per), b1 = min(r_hi, b0 + per);
+  auto xval = [&](int i) { return w.rd[w.seg_start[w.root_o[i]]] + w.root_tau[i]; };
+  const bool in_regs = per <= FRUN;  // the same for every thread
+  double x[FRUN];
+  double run = -INFINITY;
+  if (in_regs) {
+#pragma unroll
+    for (int e = 0; e < FRUN; ++e) x[e] = (b0 + e < b1) ? xval(b0 + e) : -INFINITY;
+#pragma unroll
+    for (int e = 0; e < FRUN; ++e) run = fmax(run, x[e]);
+  } else {
+    for (int i = b0; i < b1; ++i) run = fmax(run, xval(i));
+  }
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const double v = wave_incl_max(run);
+  if (lane == 63) shd[wv] = v;
   __syncthreads();
-  // absolute root values, running maximum
-  for (int base = r_lo; base < r_hi; base += FNT) {
-    const int i = base + threadIdx.x;
-    double x = -INFINITY;
-    if (i < r_hi) x = w.rd[w.seg_start[w.root_o[i]]] + w.root_tau[i];
-    double v = wave_incl_max(x);
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    __syncthreads();
-    if (lane == 63) shd[wv] = v;
-    __syncthreads();
-    double pre = s_carry;
-    for (int q = 0; q < wv; ++q) pre = fmax(pre, shd[q]);
-    v = fmax(v, pre);
-    if (i < r_hi) w.xs[i] = v;
-    __syncthreads();
-    if (threadIdx.x == FNT - 1) s_carry = v;
-    __syncthreads();
+  double pre = __shfl_up(v, 1, 64);  // the maximum over the runs of lower lanes
+  if (lane == 0) pre = -INFINITY;
+  for (int q = 0; q < wv; ++q) pre = fmax(pre, shd[q]);
+  if (in_regs) {
+#pragma unroll
+    for (int e = 0; e < FRUN; ++e) {
+      pre = fmax(pre, x[e]);
+      if (b0 + e < b1) w.xs[b0 + e] = pre;
+    }
+  } else {
+    for (int i = b0; i < b1; ++i) {
+      pre = fmax(pre, xval(i));
+      w.xs[i] = pre;
+    }
   }
 }
 
