@@ -65,6 +65,10 @@ CASES = [
     ("k=5, n=2304", lambda: wl.general_rankk(5, n=2304, seed=34)),
     ("k=8, n=2048", lambda: wl.general_rankk(8, n=2048, seed=35)),
     ("clusters and tiny rows, n=4096", lambda: wl.clustered_rank2(4096, seed=36)),
+    # the top root lies far above the spectrum: the last column block is close to
+    # six row blocks beyond its band, so it is multiplied over all rows and its
+    # product is launched first (the ragged and clusters cases move blocks with
+    # one extra pair ahead of the others)
     ("strong perturbation (||K|| ~ 10: outlying eigenvalues), n=2048",
      lambda: wl.random_small(2048, 2, seed=38, knorm=10.0)),
 ]
