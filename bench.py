@@ -56,14 +56,13 @@ def make_perturbations(n, k, count, seed, dev):
     return out
 
 
-def cpu_baseline(lam, Qn, K, sig, roots_sample, cols_sample, seed=7):
+def cpu_baseline(lam, Qn, K, sig, roots_sample, cols_sample, seed=7, threads=0):
     """Time the oracle on one whole update (default), or on a sample of its roots and
-    columns scaled to a whole update."""
+    columns scaled to a whole update; threads 0: every core this process may use."""
     import oracle
 
     n = lam.size
-    threads = len(os.sched_getaffinity(0))
-    oracle.set_threads(threads)
+    oracle.set_threads(threads if threads > 0 else len(os.sched_getaffinity(0)))
     t0 = time.perf_counter()
     U = oracle.qtk(Qn, K)
     t_u = time.perf_counter() - t0
@@ -611,6 +610,8 @@ def main():
                     help="roots the CPU oracle solves (default: all)")
     ap.add_argument("--cpu-cols", type=int, default=1 << 30,
                     help="columns of Q W the CPU oracle forms (default: all)")
+    ap.add_argument("--cpu-threads", type=int, default=0,
+                    help="threads of the CPU oracle (default 0: every core this process may use)")
     ap.add_argument("--save-input", metavar="NPZ",
                     help="only generate the resident decomposition and write it to NPZ")
     ap.add_argument("--load-input", metavar="NPZ",
@@ -924,7 +925,7 @@ def main():
         Qn = np.asfortranarray(Qn)
         K0 = np.asfortranarray(perts[0][0].cpu().numpy())
         result["cpu_baseline"] = cpu_baseline(lam0, Qn, K0, perts[0][1], args.cpu_roots,
-                                              args.cpu_cols)
+                                              args.cpu_cols, threads=args.cpu_threads)
     state.close()
     print(json.dumps(result), flush=True)
 
