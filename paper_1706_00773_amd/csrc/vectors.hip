@@ -141,14 +141,20 @@ __device__ __forceinline__ void finalize_body(const Work& w) {
   finalize_cols_body<K>(w, threadIdx.x, FNT);
 }
 
-// W tile: 256 rows x CB columns per block (block coordinates bx, by).
+// W tile: 256 rows x CB columns per block (block coordinates bx, by).  The
+// block's CB column parameters are read once into LDS (every thread needs all of
+// them; read from global memory they were a chain of dependent scalar loads).
 template <int K, int CB>
 __device__ __forceinline__ void wbuild_body(const Work& w, int bx, int by) {
+  static_assert(CB <= 256, "one thread per column parameter");
+  __shared__ ColParam s_cp[CB];
   if (update_cancelled(w.st)) return;
   const int n = w.n;
   const int r = bx * 256 + threadIdx.x;
   const int p0 = by * CB;
   const int pe = min(w.ncols, p0 + CB);
+  if ((int)threadIdx.x < pe - p0) s_cp[threadIdx.x] = w.colp[p0 + threadIdx.x];
+  __syncthreads();
   if (r >= n) return;
   const int jr = w.rmap[r];
   double dj = 0.0, u[K];
@@ -161,7 +167,7 @@ __device__ __forceinline__ void wbuild_body(const Work& w, int bx, int by) {
   }
   double* __restrict__ Wc = w.W;
   for (int p = p0; p < pe; ++p) {
-    const ColParam& cp = w.colp[p];
+    const ColParam& cp = s_cp[p - p0];
     double val;
     if (cp.drow >= 0) {
       val = (r == cp.drow) ? 1.0 : 0.0;
