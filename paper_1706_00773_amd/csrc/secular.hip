@@ -278,31 +278,50 @@ constexpr int LNT = 1024;
 
 __device__ __forceinline__ void locate_body(const Work& w) {
   __shared__ int shi[LNT / 64 + 1];
-  __shared__ int s_carry;
   if (update_cancelled(w.st)) return;
   const int n_s = w.info->n_s, n_d = w.info->n_d;
-  if (threadIdx.x == 0) s_carry = 0;
-  __syncthreads();
-  // running maximum, clamped to [0, n_d]
-  for (int base = 0; base < n_s; base += LNT) {
-    const int s = base + threadIdx.x;
-    int v = (s < n_s) ? min(max(w.nu[s], 0), n_d) : 0;
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  // running maximum, clamped to [0, n_d] (0 is the identity: the clamped counts
+  // are >= 0): each thread takes one run of consecutive counts, the runs' maxima
+  // are scanned across the block, then each run is written.  Runs of up to
+  // LRUN counts are held in registers, their loads issued together.
+  constexpr int LRUN = 16;
+  const int per = (n_s + LNT - 1) / LNT;
+  const int b0 = min(n_s, (int)threadIdx.x * per), b1 = min(n_s, b0 + per);
+  auto count = [&](int s) { return min(max(w.nu[s], 0), n_d); };
+  const bool in_regs = per <= LRUN;  // the same for every thread
+  int x[LRUN];
+  int run = 0;
+  if (in_regs) {
 #pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-      const int t = __shfl_up(v, off, 64);
-      if (lane >= off) v = max(v, t);
+    for (int e = 0; e < LRUN; ++e) x[e] = (b0 + e < b1) ? count(b0 + e) : 0;
+#pragma unroll
+    for (int e = 0; e < LRUN; ++e) run = max(run, x[e]);
+  } else {
+    for (int s = b0; s < b1; ++s) run = max(run, count(s));
+  }
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  int v = run;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const int t = __shfl_up(v, off, 64);
+    if (lane >= off) v = max(v, t);
+  }
+  if (lane == 63) shi[wv] = v;
+  __syncthreads();
+  int pre = __shfl_up(v, 1, 64);  // the maximum over the runs of lower lanes
+  if (lane == 0) pre = 0;
+  for (int q = 0; q < wv; ++q) pre = max(pre, shi[q]);
+  if (in_regs) {
+#pragma unroll
+    for (int e = 0; e < LRUN; ++e) {
+      pre = max(pre, x[e]);
+      if (b0 + e < b1) w.nu[b0 + e] = pre;
     }
-    __syncthreads();
-    if (lane == 63) shi[wv] = v;
-    __syncthreads();
-    int pre = s_carry;
-    for (int q = 0; q < wv; ++q) pre = max(pre, shi[q]);
-    v = max(v, pre);
-    if (s < n_s) w.nu[s] = v;
-    __syncthreads();
-    if (threadIdx.x == LNT - 1) s_carry = v;
-    __syncthreads();
+  } else {
+    for (int s = b0; s < b1; ++s) {
+      pre = max(pre, count(s));
+      w.nu[s] = pre;
+    }
   }
   __syncthreads();
   for (int t = threadIdx.x; t <= n_s; t += LNT) {
