@@ -421,6 +421,43 @@ int eig_server_stats(eig_server_t s, eig_server_info *info);
 /* Finish every queued request, then release everything. */
 int eig_server_destroy(eig_server_t s);
 
+/* ---------------------------------------------------------- no allocation
+ * For callers that cannot allocate device memory -- code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc: the
+ * eigenvalues of A' = A + K Sigma K^T from a decomposition the caller holds,
+ * computed by the kernels of eig_update_rankk with EIG_VALUES_ONLY, with no
+ * state and no allocation.  The workspace (U, deflation, reduced problem,
+ * roots: about 600 bytes per row) lives in one static device array of 10 MiB
+ * that each device keeps until the process ends.  Every call on a device
+ * shares that device's array and leaves its contents behind: calls that
+ * overlap on one device (different streams, or host threads) race and must
+ * be serialised by the caller.
+ *   n, k          order (1 <= n <= EIG_NOALLOC_NMAX) and rank (1 <= k <=
+ *                 min(n, EIG_KMAX))
+ *   lambda        device pointer, n values, ascending (ties allowed)
+ *   Q             device pointer, n-by-n column-major, leading dimension
+ *                 ldq >= n, orthonormal columns
+ *   K             device pointer, n-by-k column-major, leading dimension ldk >= n
+ *   sigma         host array of k entries, each +1 or -1
+ *   mode          0 or EIG_LOCATE_RESIDUES
+ *   lambda_out    device pointer, n doubles: the eigenvalues of A', ascending
+ *   status_out    device pointer to one int32: EIG_OK, or EIG_ENONFINITE /
+ *                 EIG_ENOCONV when the device found a non-finite input or a
+ *                 root that did not converge (lambda_out is then unspecified)
+ *   device        the HIP device of all pointers
+ * Asynchronous: enqueues the kernels on hip_stream (NULL = default stream)
+ * and returns; the inputs are read and the outputs written in stream order.
+ * Calls no hipMalloc, hipFree or other allocating routine.
+ * Errors (synchronous, nothing enqueued): EIG_EINVAL (NULL pointer, n < 1,
+ * k < 1, k > n, ld < n, sigma not +-1), EIG_EUNSUPPORTED (n > EIG_NOALLOC_NMAX,
+ * k > EIG_KMAX, another mode bit), EIG_EDEVICE (no such device, launch
+ * failure). */
+enum { EIG_NOALLOC_NMAX = 16384 };
+int eig_eigvals_rankk_noalloc(int64_t n, int64_t k, const double *lambda, const double *Q,
+                              int64_t ldq, const double *K, int64_t ldk, const int8_t *sigma,
+                              uint32_t mode, double *lambda_out, int32_t *status_out,
+                              int32_t device, void *hip_stream);
+
 /* Diagnostics: copy an intermediate of the last update to host memory `dst`
  * (`bytes` available) after synchronising `hip_stream`.  `what`:
  *   EIG_DBG_U            U = Q^T K, n-by-k row-major doubles

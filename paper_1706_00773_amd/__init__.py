@@ -42,6 +42,7 @@ EIG_PHASE_TIMING = 1 << 7
 EIG_LOCATE_RESIDUES = 1 << 8
 EIG_QW_FARFIELD = 1 << 9
 EIG_KMAX = 8
+EIG_NOALLOC_NMAX = 16384
 
 EIG_DBG_U = 1
 EIG_DBG_POLE_COUNT = 2
@@ -67,7 +68,8 @@ EXPORTED = ("eig_state_create", "eig_state_upload", "eig_update_rankk", "eig_upd
             "eig_state_destroy", "eig_status_str", "eig_debug_fetch", "eig_batch_create",
             "eig_update_batch", "eig_batch_set", "eig_batch_get", "eig_batch_destroy",
             "eig_server_create", "eig_server_add", "eig_server_submit", "eig_server_poll",
-            "eig_server_drain", "eig_server_read", "eig_server_stats", "eig_server_destroy")
+            "eig_server_drain", "eig_server_read", "eig_server_stats", "eig_server_destroy",
+            "eig_eigvals_rankk_noalloc")
 
 
 class eig_info(ctypes.Structure):
@@ -185,6 +187,9 @@ def load_library(path: str = LIB_PATH):
     lib.eig_server_read.argtypes = [vp, i32, vp, vp, i64, i32]
     lib.eig_server_stats.argtypes = [vp, ctypes.POINTER(eig_server_info)]
     lib.eig_server_destroy.argtypes = [vp]
+    lib.eig_eigvals_rankk_noalloc.argtypes = [i64, i64, vp, vp, i64, vp, i64,
+                                              ctypes.POINTER(ctypes.c_int8), ctypes.c_uint32,
+                                              vp, vp, i32, vp]
     for name in EXPORTED:
         getattr(lib, name).restype = (ctypes.c_char_p if name == "eig_status_str"
                                       else ctypes.c_int)
@@ -389,6 +394,32 @@ def eig_query(s, lambda_out=None, Q_out=None, stream=None, want_info: bool = Tru
                        ctypes.byref(info) if info is not None else None, st)
     _check(rc, "eig_query")
     return info
+
+
+def eig_eigvals_rankk_noalloc(lam, Q, K, sigma, lam_out, status_out, mode: int = 0,
+                              device: int = 0, stream=None) -> None:
+    """Enqueue the eigenvalues of Q diag(lam) Q^T + K diag(sigma) K^T into lam_out with
+    no device allocation (the library's static workspace).  lam, Q, K, lam_out: float64
+    torch tensors on `device` (Q, K column-major); status_out: an int32 torch tensor
+    of one element that receives the EIG_* status on the stream."""
+    import torch
+
+    n = lam.shape[0]
+    k = 1 if K.ndim == 1 else K.shape[1]
+    for t in (lam, Q, K, lam_out, status_out):
+        if not _is_torch(t) or not t.is_cuda:
+            raise TypeError("expected torch tensors on the GPU")
+    if status_out.dtype != torch.int32 or lam_out.dtype != torch.float64:
+        raise TypeError("lam_out must be float64 and status_out int32")
+    if not (lam.is_contiguous() and lam_out.is_contiguous()):
+        raise ValueError("lam and lam_out must be contiguous")
+    qp, ldq, _, qk = _colmajor_ptr(Q, n)
+    kp, ldk, _, kk = _colmajor_ptr(K, n)
+    sig = (ctypes.c_int8 * k)(*[int(v) for v in np.asarray(sigma).ravel()[:k]])
+    _check(load_library().eig_eigvals_rankk_noalloc(
+        n, k, lam.data_ptr(), qp, ldq, kp, ldk, sig, int(mode), lam_out.data_ptr(),
+        status_out.data_ptr(), int(device), _current_stream(stream)),
+        "eig_eigvals_rankk_noalloc")
 
 
 def eig_debug_fetch(s, what: int, count: int, dtype, stream=None) -> np.ndarray:

@@ -62,6 +62,19 @@ size_t carve(eig_state_s* s, void* base) {
     w.W = c.take<double>(n * n);
   }
   s->Kbuf = c.take<double>(n * KMAX);
+  c.off = carve_workspace(w, n, static_cast<char*>(base), c.off);
+  w.lp_part = c.take<double>((size_t)LP_RESID_CHUNKS * n * KMAX);
+  w.lp_resid = c.take<double>(n * KMAX);
+  return c.off + 256;
+}
+
+}  // namespace
+
+namespace eigupd {
+
+size_t carve_workspace(Work& w, size_t n, char* base, size_t off) {
+  Carver c(base);
+  c.off = off;
   w.U = c.take<double>(n * KMAX);
   w.tiny = c.take<int>(n);
   w.nt_list = c.take<int>(n);
@@ -95,12 +108,14 @@ size_t carve(eig_state_s* s, void* base) {
   w.root_it = c.take<int>(n);
   w.xs = c.take<double>(n);
   w.colp = c.take<ColParam>(n);
-  w.lp_part = c.take<double>((size_t)LP_RESID_CHUNKS * n * KMAX);
-  w.lp_resid = c.take<double>(n * KMAX);
   w.st = c.take<DevState>(1);
   w.info = c.take<DevInfo>(1);
-  return c.off + 256;
+  return c.off;
 }
+
+}  // namespace eigupd
+
+namespace {
 
 int status_from_bits(int bits) {
   if (bits & ST_NONFINITE) return EIG_ENONFINITE;
@@ -156,6 +171,7 @@ int state_create(eig_state_t* out, int64_t n, int32_t device, bool lean) {
   s->lean = lean;
   s->w.n = (int)n;
   s->w.ncols = (int)n;
+  s->w.ldq = (int)n;
   const size_t bytes = carve(s, nullptr);
   void* block = nullptr;
   if (hipMalloc(&block, bytes) != hipSuccess) {

@@ -70,7 +70,8 @@ struct ColParam {   // one output column of W
 
 struct Work {
   int n, k, ldk, sig_pos_mask;  // bit c of sig_pos_mask set <=> sigma_c = +1
-  int ncols, pad_;              // columns of W built (n, or the size of a subset)
+  int ncols;                    // columns of W built (n, or the size of a subset)
+  int ldq;                      // leading dimension of Q_in as read by U = Q^T K
   const double* lam_in;
   const double* Q_in;
   double* lam_out;

@@ -1,11 +1,13 @@
 // qtk.hip -- U = Q^T K (Sec. 2.1: U = Q^T K; Sec. 2.4 calls it L).
 //
-// Q is n-by-n column-major and K n-by-k with k <= 8, so U is a skinny product
-// bound by streaming Q from HBM once (8 n^2 bytes, 2 n^2 k flops).  A block of
-// 256 threads owns CPB consecutive columns of Q: each thread walks row pairs
-// r = 2 tid, 2 tid + 512, ... (16-byte loads, coalesced along the column; rows
-// tid, tid + 256, ... when n is odd), keeps K's rows in registers for all CPB
-// columns, and the block reduces CPB*k partial sums at the end.  Non-finite entries of U raise the sticky ST_NONFINITE bit.
+// Q is n-by-n column-major (leading dimension ldq >= n) and K n-by-k with
+// k <= 8, so U is a skinny product bound by streaming Q from HBM once
+// (8 n^2 bytes, 2 n^2 k flops).  A block of 256 threads owns CPB consecutive
+// columns of Q: each thread walks row pairs r = 2 tid, 2 tid + 512, ...
+// (16-byte loads, coalesced along the column; rows tid, tid + 256, ... when n
+// or ldq is odd), keeps K's rows in registers for all CPB columns, and the
+// block reduces CPB*k partial sums at the end.  Non-finite entries of U raise
+// the sticky ST_NONFINITE bit.
 #include "common.h"
 
 namespace eigupd {
@@ -22,8 +24,9 @@ __device__ __forceinline__ void qtk_body(const Work& w, int bid) {
     for (int c = 0; c < K; ++c) acc[q][c] = 0.0;
   const double* __restrict__ Q = w.Q_in;
   const double* __restrict__ Km = w.K;
+  const size_t ldq = (size_t)w.ldq;
   const int ncol = min(CPB, n - j0);
-  if (!(n & 1) && !((uintptr_t)Q & 15)) {
+  if (!(n & 1) && !(ldq & 1) && !((uintptr_t)Q & 15)) {
     // rows r, r + 1 (r even) in one 16-byte load per column
     for (int r = 2 * threadIdx.x; r < n; r += 512) {
       double k0[K], k1[K];
@@ -35,7 +38,7 @@ __device__ __forceinline__ void qtk_body(const Work& w, int bid) {
 #pragma unroll
       for (int q = 0; q < CPB; ++q) {
         double2 v = make_double2(0.0, 0.0);
-        if (q < ncol) v = *reinterpret_cast<const double2*>(Q + r + (size_t)(j0 + q) * n);
+        if (q < ncol) v = *reinterpret_cast<const double2*>(Q + r + (size_t)(j0 + q) * ldq);
 #pragma unroll
         for (int c = 0; c < K; ++c) acc[q][c] = fma(v.y, k1[c], fma(v.x, k0[c], acc[q][c]));
       }
@@ -47,7 +50,7 @@ __device__ __forceinline__ void qtk_body(const Work& w, int bid) {
       for (int c = 0; c < K; ++c) kr[c] = Km[r + (size_t)c * w.ldk];
 #pragma unroll
       for (int q = 0; q < CPB; ++q) {
-        const double v = (q < ncol) ? Q[r + (size_t)(j0 + q) * n] : 0.0;
+        const double v = (q < ncol) ? Q[r + (size_t)(j0 + q) * ldq] : 0.0;
 #pragma unroll
         for (int c = 0; c < K; ++c) acc[q][c] = fma(v, kr[c], acc[q][c]);
       }

@@ -30,6 +30,12 @@ struct eig_state_s {
 
 namespace eigupd {
 
+// Lays out the O(n) workspace of one update of order n (U, deflation, reduced
+// problem, roots, column parameters, status and info) at base + off, each
+// buffer 256-byte aligned; base == nullptr is a sizing pass that leaves the
+// pointers null.  Returns the offset just past the last buffer.
+size_t carve_workspace(Work& w, size_t n, char* base, size_t off);
+
 // Creates a state; lean: without its own Q buffers and W (24 n^2 bytes fewer),
 // for an owner that lends them per update.
 int state_create(eig_state_t* out, int64_t n, int32_t device, bool lean);

@@ -104,6 +104,29 @@ def test_no_device_reports_edevice():
     assert lib.eig_state_create(ctypes.byref(h), 16, 0) == eu.EIG_EDEVICE
 
 
+def test_noalloc_checks_arguments_before_the_device():
+    """The no-allocation entry point rejects bad sizes, ranks and modes before it
+    looks for a device (the pointers are never read on these paths)."""
+    import torch
+
+    lib = eu.load_library()
+    f = lib.eig_eigvals_rankk_noalloc
+    x = np.zeros(4)
+    p = x.ctypes.data
+    sig = (ctypes.c_int8 * 2)(1, -1)
+    nmax = eu.EIG_NOALLOC_NMAX
+    assert f(nmax + 1, 2, p, p, nmax + 1, p, nmax + 1, sig, 0, p, p, 0, None) == \
+        eu.EIG_EUNSUPPORTED
+    assert f(16, 9, p, p, 16, p, 16, sig, 0, p, p, 0, None) == eu.EIG_EUNSUPPORTED
+    assert f(16, 2, p, p, 16, p, 16, sig, eu.EIG_VALUES_ONLY, p, p, 0, None) == \
+        eu.EIG_EUNSUPPORTED
+    assert f(16, 2, p, p, 15, p, 16, sig, 0, p, p, 0, None) == eu.EIG_EINVAL
+    assert f(16, 2, p, p, 16, p, 16, sig, 0, p, None, 0, None) == eu.EIG_EINVAL
+    assert f(0, 2, p, p, 16, p, 16, sig, 0, p, p, 0, None) == eu.EIG_EINVAL
+    if not torch.cuda.is_available():
+        assert f(16, 2, p, p, 16, p, 16, sig, 0, p, p, 0, None) == eu.EIG_EDEVICE
+
+
 def test_c_client_compiles(tmp_path):
     """The plain C client (tests/c_client/eigupd_client.c) builds against the header
     and the library with gcc alone, no Python or torch types involved."""
