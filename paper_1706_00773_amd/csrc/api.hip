@@ -129,6 +129,17 @@ int status_from_bits(int bits) {
     if ((x) != hipSuccess) return EIG_EDEVICE;      \
   } while (0)
 
+// Writes the device status `ds` with its sticky bits cleared, and waits until
+// the write has landed: a host-to-device hipMemcpy may return before its DMA
+// ends, and a later update on a non-blocking stream would then still see the
+// old bits.
+hipError_t clear_status(DevState* dst, DevState ds, hipStream_t st) {
+  ds.status = 0;
+  hipError_t e = hipMemcpyAsync(dst, &ds, sizeof(ds), hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  return e;
+}
+
 }  // namespace
 
 extern "C" {
@@ -438,9 +449,7 @@ int eig_update_interval(eig_state_t s, int64_t k, const double* K, int64_t ldk,
   HIPCHK(hipMemcpy(&di, s->w.info, sizeof(di), hipMemcpyDeviceToHost));
   auto device_error = [&]() -> int {
     // report a device error and clear it: the state keeps its committed pair
-    DevState z = ds;
-    z.status = 0;
-    if (hipMemcpy(s->w.st, &z, sizeof(z), hipMemcpyHostToDevice) != hipSuccess) return EIG_EDEVICE;
+    if (clear_status(s->w.st, ds, st) != hipSuccess) return EIG_EDEVICE;
     return status_from_bits(ds.status);
   };
   if (ds.status != 0) return device_error();
@@ -500,9 +509,7 @@ int eig_sturm_chain(eig_state_t s, int64_t k, const double* K, int64_t ldk,
   HIPCHK(hipMemcpy(&di, s->w.info, sizeof(di), hipMemcpyDeviceToHost));
   if (ds.status != 0) {
     // report a device error and clear it: the state keeps its committed pair
-    DevState z = ds;
-    z.status = 0;
-    if (hipMemcpy(s->w.st, &z, sizeof(z), hipMemcpyHostToDevice) != hipSuccess) return EIG_EDEVICE;
+    if (clear_status(s->w.st, ds, st) != hipSuccess) return EIG_EDEVICE;
     return status_from_bits(ds.status);
   }
   if (di.n_s != di.n_d) return EIG_EUNSUPPORTED;
@@ -602,9 +609,7 @@ int eig_query(eig_state_t s, double* lambda_out, double* Q_out, int64_t ldq,
   int rc = EIG_OK;
   if (ds.status != 0) {
     rc = status_from_bits(ds.status);
-    DevState z = ds;
-    z.status = 0;
-    HIPCHK(hipMemcpy(s->w.st, &z, sizeof(z), hipMemcpyHostToDevice));
+    HIPCHK(clear_status(s->w.st, ds, st));
     s->enq_gen = ds.gen;
     s->last_vo = false;
   }

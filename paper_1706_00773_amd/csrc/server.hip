@@ -111,11 +111,13 @@ class Arena {
 
 // Moves `bytes` from src down to dst < src inside one allocation: forward
 // copies of at most src - dst bytes never overwrite source bytes not yet read.
-bool move_down(char* dst, const char* src, size_t bytes) {
+// The copies are enqueued in order on `st` (the caller synchronises it).
+bool move_down(char* dst, const char* src, size_t bytes, hipStream_t st) {
   const size_t gap = (size_t)(src - dst);
   for (size_t pos = 0; pos < bytes; pos += gap) {
     const size_t c = std::min(gap, bytes - pos);
-    if (hipMemcpy(dst + pos, src + pos, c, hipMemcpyDeviceToDevice) != hipSuccess) return false;
+    if (hipMemcpyAsync(dst + pos, src + pos, c, hipMemcpyDeviceToDevice, st) != hipSuccess)
+      return false;
   }
   return true;
 }
@@ -201,10 +203,14 @@ void retire(eig_server_s* s, Slot& sl) {
     } else {
       if (rc == EIG_OK) rc = EIG_EDEVICE;
       s->arena.release(r->q_off, nn);
-      // clear the sticky bits so that the matrix takes later updates
+      // clear the sticky bits so that the matrix takes later updates; the copy
+      // must have landed before any stream runs the matrix's next update
       DevState z = ds;
       z.status = 0;
-      if (hipMemcpy(st->w.st, &z, sizeof(z), hipMemcpyHostToDevice) != hipSuccess) rc = EIG_EDEVICE;
+      if (hipMemcpyAsync(st->w.st, &z, sizeof(z), hipMemcpyHostToDevice, sl.stream) !=
+              hipSuccess ||
+          hipStreamSynchronize(sl.stream) != hipSuccess)
+        rc = EIG_EDEVICE;
       st->enq_gen = ds.gen;
     }
     s->arena.release(r->w_off, nn);
@@ -234,8 +240,13 @@ void retire(eig_server_s* s, Slot& sl) {
 
 // Called with the lock held and nothing in flight: slides every resident Q to
 // the bottom of the arena (in offset order) so that the free space is one
-// block.  Returns false if a device copy failed.
+// block.  The moves run on the first slot's stream, which is synchronised
+// before returning: the server's streams do not wait for one another (nor for
+// the null stream, on which a device-to-device hipMemcpy may still be running
+// when it returns), and the next batch reads the moved buffers.  Returns false
+// if a device copy failed.
 bool compact(eig_server_s* s) {
+  hipStream_t st = s->slots[0].stream;
   std::vector<int> order(s->mats.size());
   for (size_t i = 0; i < order.size(); ++i) order[i] = (int)i;
   std::sort(order.begin(), order.end(),
@@ -245,12 +256,13 @@ bool compact(eig_server_s* s) {
     Matrix& m = s->mats[i];
     const size_t bytes = align_up((size_t)m.n * m.n * sizeof(double));
     if (m.q_off != top) {
-      if (!move_down(s->arena.base + top, s->arena.base + m.q_off, bytes)) return false;
+      if (!move_down(s->arena.base + top, s->arena.base + m.q_off, bytes, st)) return false;
       m.q_off = top;
       m.st->Q[m.st->enq_gen & 1] = s->arena.ptr(top);
     }
     top += bytes;
   }
+  if (hipStreamSynchronize(st) != hipSuccess) return false;
   s->arena.reset_free(top);
   s->compactions += 1;
   return true;
@@ -528,6 +540,9 @@ int eig_server_add(eig_server_t s, int64_t n, const double* lambda, const double
                      kind) == hipSuccess;
     DevState z{};
     ok = ok && hipMemcpy(st->w.st, &z, sizeof(z), hipMemcpyHostToDevice) == hipSuccess;
+    // the copies above may still be in flight (device-to-device, or the DMA of
+    // a staged host copy); the server's streams do not wait for them
+    ok = ok && hipDeviceSynchronize() == hipSuccess;
   }
   if (!ok || rc != EIG_OK) {
     s->arena.release(q_off, nn);
@@ -636,6 +651,8 @@ int eig_server_read(eig_server_t s, int32_t matrix, double* lambda_out, double* 
                            (size_t)m.n * sizeof(double), (size_t)m.n * sizeof(double),
                            (size_t)m.n, kind) != hipSuccess)
     return EIG_EDEVICE;
+  // device-to-device copies may return before they finish
+  if (ptrs_on_device && hipDeviceSynchronize() != hipSuccess) return EIG_EDEVICE;
   return EIG_OK;
 }
 

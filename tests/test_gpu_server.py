@@ -184,3 +184,53 @@ def test_server_argument_errors():
             srv.add(lam_bad, mats[0][1])
         assert e.value.code == eu.EIG_ENOTSORTED
         assert srv.stats()["submitted"] == 0
+
+
+def test_serving_large_matrices_alone_and_in_the_mix():
+    """The serving workload's shape at its large end: matrices of n = 2048 to
+    8192 (random orthogonal Q, lambda uniform in [-1, 1]) next to small ones,
+    requests of rank 1, 2, 4 and 8 with K ~ N(0, 1/n), random signs.  Every
+    matrix ends bitwise where its updates applied alone leave it; the last
+    update of each large matrix is checked against the oracle applied to the
+    decomposition it started from (all eigenvalues of n = 2048 and a 128-value
+    sample of the others, within 1e-10 ||A'||_2)."""
+    import torch
+
+    dev = "cuda:0"
+    sizes = [8192, 2048, 300, 4096, 3000, 700]
+    print(f"case serving large matrices: sizes {sizes}, 28 requests", flush=True)
+    rng = np.random.default_rng(1005)
+    mats = []
+    for n in sizes:
+        lam = wl.distinct_uniform(n, -1.0, 1.0, 1e-12, rng)
+        Qt = wl.orthogonal_from(wl.gaussian_square(n, rng), dev)
+        mats.append((lam, np.asfortranarray(Qt.cpu().numpy())))
+        del Qt
+    reqs = _requests(sizes, 28, rng)
+    arena = sum(24 * n * n for n in sizes)
+    comps, finals, stats = _serve(mats, reqs, arena=arena, max_batch=8, streams=2,
+                                  spread_s=0.002)
+    assert len(comps) == 28 and all(c["status"] == eu.EIG_OK for c in comps)
+    assert stats["completed"] == 28 and stats["failed"] == 0
+    for m, (lam, Q) in enumerate(mats):
+        ups = [(K, sig) for rid, mm, K, sig in reqs if mm == m]
+        if not ups:
+            continue
+        la, Qa = _alone(lam, Q, ups)
+        assert np.array_equal(finals[m][0], la), m
+        assert np.array_equal(finals[m][1], Qa), m
+        n = sizes[m]
+        if n < 2048:
+            continue
+        # the oracle on the last update, from the decomposition before it
+        lp, Qp = _alone(lam, Q, ups[:-1]) if len(ups) > 1 else (lam, Q)
+        K, sig = ups[-1]
+        U = oracle.qtk(np.asfortranarray(Qp), K)
+        scale = np.abs(lp).max() + float(np.sum(U * U))
+        idx = None if n == 2048 else np.sort(rng.choice(n, 128, replace=False))
+        ref = oracle.eigvals(lp, U, sig, idx)[0]
+        got = la if idx is None else la[idx]
+        de = np.abs(got - ref).max() / scale
+        print(f"  matrix {m} n={n}: {len(ups)} updates, last k={K.shape[1]}: eig {de:.1e}",
+              flush=True)
+        assert de <= 1e-10
