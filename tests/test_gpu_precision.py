@@ -131,3 +131,91 @@ def test_unknown_precision_selector_rejected():
         with pytest.raises(eu.EigError) as e:
             s.update(K, np.array([1]), eu.EIG_GEMM_MASK)
         assert e.value.code == eu.EIG_EUNSUPPORTED
+
+
+@pytest.fixture(scope="module")
+def logspread_n16384():
+    """The n = 16384, k = 4 log-spread workload on the device, with the oracle's
+    U, a seeded sample of 512 eigenvalues, and eq. (10) vectors in the Q basis
+    for 256 sampled columns with isolated eigenvalues."""
+    print("case logspread rank-4 n=16384: oracle", flush=True)
+    u = wl.logspread_rankk(4, n=16384, device="cuda:0")
+    n = u.lam.size
+    Qh = np.asfortranarray(u.Q.cpu().numpy())
+    U = oracle.qtk(Qh, u.K)
+    del Qh
+    scale = np.abs(u.lam).max() + float(np.sum(U * U))
+    rng = np.random.default_rng(16384)
+    idx = np.unique(np.r_[rng.choice(n, 512, replace=False), 0, n - 1])
+    vals, org, tau, _ = oracle.eigvals(u.lam, U, u.sigma, idx)
+    d = np.diff(vals)
+    gaps = np.minimum(np.r_[d, np.inf], np.r_[np.inf, d])
+    # a sampled value is isolated when its neighbours in the sample are far; the
+    # device's own neighbours are checked in the test
+    iso = np.nonzero(gaps > 1e-6 * scale)[0][:256]
+    Wv = oracle.eigvecs(u.lam, U, u.sigma, org[iso], tau[iso])
+    return dict(u=u, U=U, scale=scale, idx=idx, vals=vals, iso=iso, Wv=Wv)
+
+
+@pytest.mark.parametrize("mode", list(MODES))
+def test_reduced_precision_n16384(logspread_n16384, mode):
+    """The mixed-precision workload at its full size (n = 16384, k = 4): U and the
+    eigenvalues at the FP64 bar, Q W within QW_TOL of the FP64 product of the same
+    Q and W, W's columns against the oracle's eq. (10) vectors, and the residual
+    and orthogonality of every column within 2 sqrt(n) QW_TOL."""
+    import torch
+
+    c = logspread_n16384
+    u, scale, dev = c["u"], c["scale"], "cuda:0"
+    n, k = u.lam.size, u.K.shape[1]
+    print(f"case mode={mode} n={n} k={k}: update", flush=True)
+    Kt = torch.from_numpy(np.ascontiguousarray(np.asarray(u.K).T)).to(dev).t()
+    with eu.EigState(n, 0) as s:
+        s.upload(torch.from_numpy(u.lam).to(dev), u.Q)
+        s.update(Kt, u.sigma, MODES[mode])
+        lo = torch.empty(n, dtype=torch.float64, device=dev)
+        Qo = torch.empty((n, n), dtype=torch.float64, device=dev).t()
+        s.query(lo, Qo)
+        Ug = s.fetch(eu.EIG_DBG_U, n * k).reshape(n, k)
+        Wh = s.fetch(eu.EIG_DBG_W, n * n).reshape(n, n, order="F")
+    du = np.abs(Ug - c["U"]).max() / np.abs(c["U"]).max()
+    assert du <= 1e-13, du
+    lam_g = lo.cpu().numpy()
+    assert np.all(np.diff(lam_g) >= 0.0)
+    de = np.abs(lam_g[c["idx"]] - c["vals"]).max() / scale
+    assert de <= EVAL_TOL, de
+    sig = u.sigma.astype(float)
+    tr = float(np.sum(sig * np.sum(np.asarray(u.K) ** 2, axis=0)))
+    assert abs((lam_g.sum() - u.lam.sum()) - tr) <= 1e-12 * n * scale
+    # W's sampled columns (isolated on the device too) against the oracle's vectors
+    cols = c["idx"][c["iso"]]
+    d = np.diff(lam_g)
+    gaps = np.minimum(np.r_[d, np.inf], np.r_[np.inf, d])
+    keep = gaps[cols] > 1e-6 * scale
+    Wg = Wh[:, cols[keep]]
+    Wr = c["Wv"][:, keep]
+    sgn = np.sign(np.sum(Wg * Wr, axis=0))
+    dv = np.abs(Wg * sgn - Wr).max()
+    assert dv <= VEC_TOL, dv
+    # the reduced product against the FP64 product of the same Q and W
+    W_t = torch.from_numpy(np.ascontiguousarray(Wh.T)).to(dev).t()
+    del Wh
+    dqw = float((u.Q @ W_t - Qo).abs().max())
+    del W_t
+    assert dqw <= QW_TOL, dqw
+    # residual of every column and orthogonality of the whole matrix
+    lam_t = torch.from_numpy(u.lam).to(dev)
+    sig_t = torch.from_numpy(sig).to(dev)
+    R = u.Q @ (lam_t[:, None] * (u.Q.t() @ Qo))
+    R += Kt @ (sig_t[:, None] * (Kt.t() @ Qo))
+    R -= Qo * lo[None, :]
+    res = float(torch.linalg.vector_norm(R, dim=0).max()) / scale
+    del R
+    G = Qo.t() @ Qo
+    G.diagonal().sub_(1.0)
+    orth = float(G.abs().max())
+    del G
+    bound = 2.0 * math.sqrt(n) * QW_TOL
+    print(f"  U {du:.1e}  eig {de:.1e}  QW {dqw:.1e}  W-vec {dv:.1e} ({int(keep.sum())} cols)  "
+          f"res {res:.1e}  orth {orth:.1e}", flush=True)
+    assert res <= bound and orth <= bound

@@ -105,6 +105,43 @@ def test_jacobi_bruteforce_matches_lapack(n):
     assert np.abs(V.T @ V - np.eye(n)).max() <= 1e-12
 
 
+@pytest.mark.parametrize("n,k,seed", [(2, 1, 1), (7, 2, 2), (16, 3, 3), (33, 4, 4), (48, 8, 5),
+                                      (64, 2, 6), (64, 8, 7)])
+def test_update_matches_jacobi_bruteforce(n, k, seed):
+    """The secular oracle's whole update (count bisection, eq. (10) vectors, Q W)
+    against the brute-force cyclic Jacobi eigensolve of the explicit A' (a
+    different algorithm on a different matrix: A' formed in FP64)."""
+    u = wl.random_small(n, k, seed=1000 + seed, knorm=1.5)
+    A = _explicit(u)
+    w, V = oracle.jacobi(A)
+    lo, Qo, _ = oracle.update(u.lam, u.Q, u.K, u.sigma)
+    scale = max(1.0, np.abs(w).max())
+    assert np.abs(lo - w).max() <= 1e-13 * scale
+    assert np.abs(A @ Qo - Qo * lo).max() <= 1e-13 * scale
+    gaps = np.full(n, np.inf)
+    if n > 1:
+        d = np.diff(w)
+        gaps[:-1] = d
+        gaps[1:] = np.minimum(gaps[1:], d)
+    iso = np.nonzero(gaps > 1e-6 * scale)[0]
+    assert iso.size >= n // 2
+    for i in iso:
+        s = np.sign(Qo[:, i] @ V[:, i])
+        assert np.abs(Qo[:, i] - s * V[:, i]).max() <= 1e-10
+
+
+def test_config_one_matches_jacobi_bruteforce():
+    """The n = 200 rank-2 column-row workload: all eigenvalues of the oracle's
+    update against brute-force Jacobi on the explicit A'."""
+    u = wl.plain_rank2(200, seed=1001)
+    A = _explicit(u)
+    w, V = oracle.jacobi(A)
+    lo, Qo, _ = oracle.update(u.lam, u.Q, u.K, u.sigma)
+    scale = np.abs(w).max()
+    assert np.abs(lo - w).max() <= 1e-13 * scale
+    assert np.abs(np.abs(np.sum(Qo * V, axis=0)) - 1.0).max() <= 1e-9
+
+
 def _dyadic_instance(n, k, seed):
     rng = np.random.default_rng(seed)
     lam = np.sort(rng.choice(np.arange(-40, 41), size=n, replace=False)) / 8.0
