@@ -125,10 +125,16 @@ enum {
                                expansions of 1/(x - y) (blocks of 256 rows and
                                columns, 24 nodes per interval): a band of exact
                                block products plus three small products, about
-                               8x fewer flops at n = 8192.  Q' agrees with the
-                               dense product to rounding level (the interpolation
-                               error is below 1e-15 for blocks at least half
-                               their width apart).  Falls back to the dense
+                               8x fewer flops at n = 8192.  A row block and a
+                               column block count as far when their distance is
+                               at least half the larger width; there the
+                               interpolant of 1/(x - y) errs by at most about
+                               1e-13 relative (Bernstein parameter 2 + sqrt(3),
+                               24 nodes), and by about 2e-15 for blocks one
+                               width apart.  The far entries of W are small
+                               next to the near ones, so Q' agrees with the
+                               dense product to about 1e-15 in practice.
+                               Falls back to the dense
                                product on the device when the update merged
                                equal poles; ignored for n < 2048, for
                                n >= 2049 * 256 and with the

@@ -3,9 +3,13 @@
 The mode changes only how Q W is formed, so:
 - its eigenvalues must be bitwise those of the dense path;
 - its Q' must agree with the dense product entrywise within 1e-12 (the
-  Chebyshev interpolation error of 1/(x - y) on blocks at least half their width
-  apart is below 1e-15 relative; the margin covers sums over n = 8192 terms of
-  entries below 1);
+  Chebyshev interpolation of 1/(x - y) on blocks at least half their width apart
+  errs by at most about 1e-13 relative, and far entries of W are small next to
+  near ones; the margin covers sums over n = 8192 terms of entries below 1);
+- on block pairs placed at that acceptance distance, with Q = I and k = 1 (so
+  that Q' is the effective W entry by entry), every entry outside the band has
+  a relative error below 1.5e-13 (7.5e-14 expected from the interpolant at
+  exactly half a width);
 - against the oracle's matrix A' it must meet the tolerances of every update
   (eigenvalues 1e-10 ||A'||, residual 1e-9 ||A'||, ||Q'^T Q' - I||_max 1e-9).
 Where the plan must fall back (merged equal poles, or half or more of the
@@ -230,3 +234,71 @@ def test_full_size_n8192(name, make):
     G = (Qf.t() @ Qf[:, cols]).cpu().numpy()
     G[cols, np.arange(cols.size)] -= 1.0
     assert np.abs(G).max() <= ORTH_TOL
+
+
+def _boundary_spectrum(eta, margin, rng):
+    """8 blocks of 256 poles: even blocks span exactly one unit, odd blocks are
+    1e-3 wide and sit in the gaps; block b + 2 starts eta (1 + margin) after the
+    end of block b, so that every pair of even blocks two apart is just far."""
+    lam, s, end = [], 0.0, 0.0
+    for b in range(8):
+        if b % 2 == 0:
+            v = s + np.sort(rng.uniform(0.0, 1.0, 256))
+            v[0], v[-1] = s, s + 1.0
+            lam.append(v)
+            end = s + 1.0
+            s = end + eta * (1.0 + margin)
+        else:
+            lam.append(end + 0.5 * eta + np.sort(rng.uniform(-5e-4, 5e-4, 256)))
+    return np.concatenate(lam)
+
+
+def test_far_pair_at_the_acceptance_boundary():
+    """Row and column blocks whose distance is 0.5 (1 + 2e-4) times the larger
+    width: the closest pairs the plan still expands.  With Q = I and k = 1 the
+    product Q W is W itself, W(j, p) = u_j c_p / (x_p - lambda_j) with no
+    cancellation, so the far-field result divided by the dense one measures the
+    error of the Chebyshev expansion entry by entry."""
+    import torch
+
+    dev = "cuda:0"
+    rng = np.random.default_rng(2026)
+    lam = _boundary_spectrum(0.5, 2e-4, rng)
+    n = lam.size
+    print(f"case far pair at the acceptance boundary: n={n} k=1", flush=True)
+    K = rng.normal(0.0, np.sqrt(0.01 / n), (n, 1))
+    sig = np.array([1], dtype=np.int8)
+    Qi = torch.eye(n, dtype=torch.float64, device=dev)
+    outs = []
+    for mode in (0, FF):
+        with eu.EigState(n, 0) as s:
+            s.upload(torch.from_numpy(lam).to(dev), Qi)
+            s.update(colmajor(K, dev), sig, mode)
+            lo = torch.empty(n, dtype=torch.float64, device=dev)
+            Qo = torch.empty((n, n), dtype=torch.float64, device=dev).t()
+            info = s.query(lo, Qo)
+            assert info.n_deflated_rows == 0
+        outs.append((lo.cpu().numpy(), Qo.cpu().numpy()))
+    (ld, Wd), (lf, Wf) = outs
+    assert np.array_equal(ld, lf)
+    assert not np.array_equal(Wd, Wf)  # the far-field path ran
+    # the block pairs two or more apart, and how far apart they are
+    B, nb = 256, n // 256
+    ratios = []
+    for I in range(nb):
+        xlo, xhi = ld[I * B], ld[I * B + B - 1]
+        for J in range(nb):
+            if abs(I - J) >= 2:
+                ylo, yhi = lam[J * B], lam[J * B + B - 1]
+                dist = max(xlo - yhi, ylo - xhi)
+                ratios.append(dist / max(xhi - xlo, yhi - ylo))
+    ratios = np.array(ratios)
+    assert ratios.min() >= 0.5 and ratios.min() <= 0.5003, ratios.min()
+    assert np.sum(ratios <= 0.5003) >= 6
+    # relative error of every entry outside the band
+    blk = np.arange(n) // B
+    off = np.abs(blk[:, None] - blk[None, :]) >= 2
+    rel = np.abs(Wf - Wd)[off] / np.abs(Wd)[off]
+    print(f"  closest far pair {ratios.min():.5f} widths apart; max relative error of the "
+          f"{off.sum()} entries outside the band {rel.max():.2e}", flush=True)
+    assert rel.max() <= 1.5e-13, rel.max()
