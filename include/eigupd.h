@@ -77,9 +77,10 @@ enum {
   EIG_ENOCONV = -4,      /* a root did not converge within the evaluation cap */
   EIG_ENOTSORTED = -5,   /* uploaded lambda not ascending */
   EIG_EUNSUPPORTED = -6, /* k beyond EIG_KMAX or a mode not built */
-  EIG_EDEPENDENCY = -7,  /* reserved: a predecessor update failed */
+  EIG_EDEPENDENCY = -7,  /* serving: an earlier update of the matrix failed */
   EIG_ESTATE = -8,       /* state not uploaded */
-  EIG_ENONFINITE = -9    /* NaN or Inf in an input or in U */
+  EIG_ENONFINITE = -9,   /* NaN or Inf in an input or in U */
+  EIG_ECHECK = -10       /* a check of EIG_DEBUG_CHECKS failed */
 };
 
 /* Mode bits of eig_update_rankk.  Bits 0-1 select the arithmetic of the two
@@ -110,6 +111,21 @@ enum {
   EIG_GEMM_MASK = 3,
   EIG_VALUES_ONLY = 1 << 4, /* eigenvalues only: nothing is committed, eig_query
                                returns these values until the next update */
+  EIG_DEBUG_CHECKS = 1 << 5, /* after the update and before its commit, check on
+                                the device: the new eigenvalues ascend, each lies
+                                in its Courant-Weyl window [lambda_{i-q},
+                                lambda_{i+p}] (Sec. 2.2) and their sum changes by
+                                sum_c sigma_c ||U_c||^2 (the trace of K Sigma
+                                K^T); unless values-only, 8 sampled columns of W
+                                solve the eigenproblem of diag(lambda) + U Sigma
+                                U^T (Sec. 2.4, eq. (10)) to 1e-9 ||A'|| and are
+                                orthonormal to 1e-9 (not with EIG_QW_FARFIELD,
+                                whose W is partial), and the same columns of Q'
+                                are orthonormal to 1e-9 (FP64) or 8e-6 sqrt(n)
+                                (reduced modes).  A failed check is the deferred
+                                error EIG_ECHECK: nothing is committed.  One
+                                small extra kernel; a non-orthogonal uploaded Q
+                                is the usual cause */
   EIG_HOST_INPUT = 1 << 6,  /* K is a host pointer (copied before return) */
   EIG_PHASE_TIMING = 1 << 7, /* record HIP events between the phases on hip_stream;
                                 eig_query reports the times in eig_info.ms */
@@ -157,6 +173,16 @@ enum { EIG_KMAX = 8 };
  * On success *out owns the memory until eig_state_destroy. */
 int eig_state_create(eig_state_t *out, int64_t n, int32_t device);
 
+/* Knobs of a state (eig_state_set).
+ *   EIG_KNOB_MAX_EVALS  evaluations (count and Newton steps together) allowed
+ *                       per root before the zero finder of Sec. 2.3 gives up
+ *                       and the update fails with the deferred EIG_ENOCONV;
+ *                       1 <= value <= 1000000, default 160.  Applies to the
+ *                       updates enqueued after the call.
+ * Errors: EIG_EINVAL (unknown knob, value out of range). */
+enum { EIG_KNOB_MAX_EVALS = 6 };
+int eig_state_set(eig_state_t s, int32_t knob, int64_t value);
+
 /* Load a decomposition: lambda (n values, ascending, ties allowed) and Q
  * (n-by-n column-major, leading dimension ldq >= n, columns orthonormal).
  * ptrs_on_device != 0: both are device pointers on the state's device.
@@ -173,6 +199,7 @@ int eig_state_upload(eig_state_t s, const double *lambda, const double *Q, int64
  *   sigma  host array of k entries, each +1 or -1
  *   mode   one of EIG_GEMM_FP64, EIG_GEMM_FP32_CORR, EIG_GEMM_BF16X3_CORR,
  *          optionally | EIG_VALUES_ONLY | EIG_HOST_INPUT | EIG_PHASE_TIMING
+ *          | EIG_LOCATE_RESIDUES | EIG_QW_FARFIELD | EIG_DEBUG_CHECKS
  * Asynchronous: enqueues the kernels on `hip_stream` and returns.  On the
  * device the update writes the new pair into the state's other buffer and
  * commits it only if no error was raised; the state then holds A'.
@@ -180,7 +207,7 @@ int eig_state_upload(eig_state_t s, const double *lambda, const double *Q, int64
  * unknown mode bit, or precision selector 3), EIG_ENOMEM (slice planes of a
  * reduced mode could not be allocated),
  * EIG_ESTATE (no upload yet), EIG_EDEVICE (launch failure).  Deferred:
- * EIG_ENONFINITE, EIG_ENOCONV (see the file header). */
+ * EIG_ENONFINITE, EIG_ENOCONV, EIG_ECHECK (see the file header). */
 int eig_update_rankk(eig_state_t s, int64_t k, const double *K, int64_t ldk,
                      const int8_t *sigma, uint32_t mode, void *hip_stream);
 
@@ -359,7 +386,12 @@ int eig_batch_destroy(eig_batch_t b);
  * (continuous batching).  Updates of one matrix run in arrival order, one at a
  * time, each on the decomposition its predecessor committed; a request's
  * result is therefore the same as applying the same updates to that matrix
- * alone.
+ * alone.  As on a single state (where a failed update turns the later ones
+ * into no-ops until eig_query), a request that fails on the device leaves its
+ * matrix unchanged, and every later request of that matrix completes with
+ * EIG_EDEPENDENCY without being applied until eig_server_read of that matrix:
+ * an update is never applied to a decomposition other than the one its
+ * predecessors were meant to produce.
  *
  * Memory: one device arena of arena_bytes holds every n x n buffer.  A
  * resident matrix keeps its current Q there (8 n^2 bytes; lambda and O(n k)
@@ -375,7 +407,9 @@ typedef struct {
   int64_t request_id; /* the caller's tag */
   int32_t matrix;
   int32_t status;     /* EIG_OK, or the error of this update (EIG_ENONFINITE,
-                         EIG_ENOCONV, EIG_ENOMEM if it could never fit, ...) */
+                         EIG_ENOCONV, EIG_ENOMEM if it could never fit,
+                         EIG_EDEPENDENCY if an earlier update of the matrix
+                         failed and the matrix was not read since, ...) */
   double t_submit;    /* seconds since eig_server_create */
   double t_admit;     /* its batch was enqueued */
   double t_done;      /* the scheduler saw its batch finish */
@@ -418,7 +452,8 @@ int eig_server_poll(eig_server_t s, eig_completion *out, int32_t max, int32_t ti
 int eig_server_drain(eig_server_t s);
 
 /* Copy out a matrix's current decomposition after its queued updates have
- * finished (waits for them). */
+ * finished (waits for them).  Clears the matrix's failed mark: requests
+ * submitted afterwards are applied again. */
 int eig_server_read(eig_server_t s, int32_t matrix, double *lambda_out, double *Q_out,
                     int64_t ldq, int32_t ptrs_on_device);
 

@@ -31,12 +31,14 @@ EIG_EUNSUPPORTED = -6
 EIG_EDEPENDENCY = -7
 EIG_ESTATE = -8
 EIG_ENONFINITE = -9
+EIG_ECHECK = -10
 
 EIG_GEMM_FP64 = 0
 EIG_GEMM_FP32_CORR = 1
 EIG_GEMM_BF16X3_CORR = 2
 EIG_GEMM_MASK = 3
 EIG_VALUES_ONLY = 1 << 4
+EIG_DEBUG_CHECKS = 1 << 5
 EIG_HOST_INPUT = 1 << 6
 EIG_PHASE_TIMING = 1 << 7
 EIG_LOCATE_RESIDUES = 1 << 8
@@ -59,11 +61,12 @@ EIG_KNOB_GEMM_TILE = 2
 EIG_KNOB_GRAPHS = 3
 EIG_STAT_GRAPH_LAUNCHES = 4
 EIG_STAT_GRAPHS_CACHED = 5
+EIG_KNOB_MAX_EVALS = 6
 EIG_AUTO = 0
 EIG_ROOTSOLVE_GROUPED = 1
 EIG_ROOTSOLVE_PERSISTENT = 2
 
-EXPORTED = ("eig_state_create", "eig_state_upload", "eig_update_rankk", "eig_update_interval",
+EXPORTED = ("eig_state_create", "eig_state_set", "eig_state_upload", "eig_update_rankk", "eig_update_interval",
             "eig_perturb_first_order", "eig_sturm_chain", "eig_query",
             "eig_state_destroy", "eig_status_str", "eig_debug_fetch", "eig_batch_create",
             "eig_update_batch", "eig_batch_set", "eig_batch_get", "eig_batch_destroy",
@@ -159,6 +162,7 @@ def load_library(path: str = LIB_PATH):
     vp, i64, i32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32
     lib.eig_state_create.argtypes = [ctypes.POINTER(vp), i64, i32]
     lib.eig_state_upload.argtypes = [vp, vp, vp, i64, i32, vp]
+    lib.eig_state_set.argtypes = [vp, i32, i64]
     lib.eig_update_rankk.argtypes = [vp, i64, vp, i64, ctypes.POINTER(ctypes.c_int8),
                                      ctypes.c_uint32, vp]
     lib.eig_query.argtypes = [vp, vp, vp, i64, i32, ctypes.POINTER(eig_info), vp]
@@ -242,6 +246,10 @@ def eig_state_create(n: int, device: int = 0):
     _check(load_library().eig_state_create(ctypes.byref(h), int(n), int(device)),
            "eig_state_create")
     return h
+
+
+def eig_state_set(s, knob: int, value: int) -> None:
+    _check(load_library().eig_state_set(s, int(knob), int(value)), "eig_state_set")
 
 
 def eig_state_destroy(s) -> None:
@@ -601,6 +609,9 @@ class EigState:
 
     def upload(self, lam, Q, stream=None):
         eig_state_upload(self.handle, lam, Q, stream)
+
+    def set(self, knob: int, value: int):
+        eig_state_set(self.handle, knob, value)
 
     def update(self, K, sigma, mode: int = EIG_GEMM_FP64, stream=None):
         eig_update_rankk(self.handle, K, sigma, mode, stream)

@@ -17,7 +17,8 @@ LIB = os.path.join(HERE, "libeigupd.so")
 BUILD_DIR = os.path.join(ROOT, "_build")
 
 SOURCES = ["api.hip", "batch.hip", "server.hip", "qtk.hip", "deflate.hip", "secular.hip",
-           "vectors.hip", "gemm.hip", "precision.hip", "chain.hip", "farfield.hip", "noalloc.hip"]
+           "vectors.hip", "gemm.hip", "precision.hip", "chain.hip", "farfield.hip", "noalloc.hip",
+           "checks.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -117,12 +117,7 @@ size_t carve_workspace(Work& w, size_t n, char* base, size_t off) {
 
 namespace {
 
-int status_from_bits(int bits) {
-  if (bits & ST_NONFINITE) return EIG_ENONFINITE;
-  if (bits & ST_NOCONV) return EIG_ENOCONV;
-  if (bits) return EIG_EDEVICE;
-  return EIG_OK;
-}
+int status_from_bits(int bits) { return status_code(bits); }
 
 #define HIPCHK(x)                                   \
   do {                                              \
@@ -156,6 +151,7 @@ const char* eig_status_str(int status) {
     case EIG_EDEPENDENCY: return "a predecessor update failed";
     case EIG_ESTATE: return "state has no decomposition (upload first)";
     case EIG_ENONFINITE: return "non-finite value in the input";
+    case EIG_ECHECK: return "a check of EIG_DEBUG_CHECKS failed";
     default: return "unknown status";
   }
 }
@@ -183,6 +179,7 @@ int state_create(eig_state_t* out, int64_t n, int32_t device, bool lean) {
   s->w.n = (int)n;
   s->w.ncols = (int)n;
   s->w.ldq = (int)n;
+  s->w.max_evals = MAX_EVALS;
   const size_t bytes = carve(s, nullptr);
   void* block = nullptr;
   if (hipMalloc(&block, bytes) != hipSuccess) {
@@ -231,6 +228,18 @@ int eig_state_destroy(eig_state_t s) {
   return EIG_OK;
 }
 
+int eig_state_set(eig_state_t s, int32_t knob, int64_t value) {
+  if (!s) return EIG_EINVAL;
+  switch (knob) {
+    case EIG_KNOB_MAX_EVALS:
+      if (value < 1 || value > 1000000) return EIG_EINVAL;
+      s->w.max_evals = (int)value;
+      return EIG_OK;
+    default:
+      return EIG_EINVAL;
+  }
+}
+
 int eig_state_upload(eig_state_t s, const double* lambda, const double* Q, int64_t ldq,
                      int32_t ptrs_on_device, void* hip_stream) {
   if (!s || !lambda || !Q || ldq < s->n || s->lean) return EIG_EINVAL;
@@ -268,7 +277,7 @@ int eig_update_rankk(eig_state_t s, int64_t k, const double* K, int64_t ldk, con
   if (k > EIG_KMAX) return EIG_EUNSUPPORTED;
   if (k > s->n) return EIG_EINVAL;
   const uint32_t known = EIG_GEMM_MASK | EIG_VALUES_ONLY | EIG_HOST_INPUT | EIG_PHASE_TIMING |
-                         EIG_LOCATE_RESIDUES | EIG_QW_FARFIELD;
+                         EIG_LOCATE_RESIDUES | EIG_QW_FARFIELD | EIG_DEBUG_CHECKS;
   if (mode & ~known) return EIG_EUNSUPPORTED;
   const int prec = (int)(mode & EIG_GEMM_MASK);
   if (prec != EIG_GEMM_FP64 && prec != EIG_GEMM_FP32_CORR && prec != EIG_GEMM_BF16X3_CORR)
@@ -363,9 +372,11 @@ int eig_update_rankk(eig_state_t s, int64_t k, const double* K, int64_t ldk, con
   HIPCHK(mark(4));
   s->last_k = (int)k;
   s->timed = timed;
+  const bool checks = (mode & EIG_DEBUG_CHECKS) != 0;
   if (vo) {
     w.lam_fin = s->lam_vo;
     HIPCHK(launch_finalize(w, st));
+    if (checks) HIPCHK(launch_debug_checks(w, false, false, 0.0, st));
     HIPCHK(mark(5));
     HIPCHK(mark(6));
     HIPCHK(mark(7));
@@ -393,6 +404,12 @@ int eig_update_rankk(eig_state_t s, int64_t k, const double* K, int64_t ldk, con
     HIPCHK(launch_gemm_lp(w, prec, s->lp_block,
                           static_cast<char*>(s->lp_block) + s->lp_bytes / 2, st));
   HIPCHK(mark(6));
+  if (checks) {
+    // W is whole unless the far-field product formed only its near blocks; the
+    // reduced products' bound on Q'^T Q' - I is 2 sqrt(n) 4e-6
+    const double tol_q = (prec == EIG_GEMM_FP64) ? 1e-9 : 8e-6 * std::sqrt((double)n);
+    HIPCHK(launch_debug_checks(w, !farfield, true, tol_q, st));
+  }
   HIPCHK(launch_commit(w, st));
   HIPCHK(mark(7));
   HIPCHK(mark(8));

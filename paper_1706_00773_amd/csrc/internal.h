@@ -27,6 +27,16 @@ constexpr int KMAX = 8;
 constexpr int ST_NONFINITE = 1;
 constexpr int ST_NOCONV = 2;
 constexpr int ST_INTERNAL = 4;
+constexpr int ST_CHECK = 8;  // a check of EIG_DEBUG_CHECKS failed
+
+// The EIG_* status of a set of deferred error bits (the first kind wins).
+__host__ __device__ inline int status_code(int bits) {
+  if (bits & ST_NONFINITE) return EIG_ENONFINITE;
+  if (bits & ST_NOCONV) return EIG_ENOCONV;
+  if (bits & ST_CHECK) return EIG_ECHECK;
+  if (bits) return EIG_EDEVICE;
+  return EIG_OK;
+}
 
 // Deflation thresholds, relative to ahat = max|lambda| + ||U||_F^2 (>= ||A'||_2):
 // a row u_j is dropped when ||u_j|| ||U||_F <= TAU_ROW * ahat; neighbouring poles
@@ -34,7 +44,8 @@ constexpr int ST_INTERNAL = 4;
 constexpr double TAU_ROW = 1e-12;
 constexpr double TAU_GAP = 8.0 * 1.1102230246251565e-16;
 
-// Iteration cap per root (count and Newton evaluations together).
+// Default iteration cap per root (count and Newton evaluations together);
+// eig_state_set(EIG_KNOB_MAX_EVALS) changes it per state.
 constexpr int MAX_EVALS = 160;
 
 // Column chunks of the FP64 residual K - Q U0 in the reduced-precision modes.
@@ -72,6 +83,8 @@ struct Work {
   int n, k, ldk, sig_pos_mask;  // bit c of sig_pos_mask set <=> sigma_c = +1
   int ncols;                    // columns of W built (n, or the size of a subset)
   int ldq;                      // leading dimension of Q_in as read by U = Q^T K
+  int max_evals;                // evaluations per root before ST_NOCONV is raised
+  int pad2_;
   const double* lam_in;
   const double* Q_in;
   double* lam_out;
@@ -220,6 +233,12 @@ hipError_t launch_wbuild_ff(const Work& w, const FarField& f, hipStream_t s);
 // Both product paths (one of them exits at once): Q_out = Q_in W.  Needs the
 // plan and W (launch_wbuild_ff, then group reflectors) to have run.
 hipError_t launch_qw_farfield(const Work& w, const FarField& f, hipStream_t s);
+
+// EIG_DEBUG_CHECKS (checks.hip): eigenvalue order, Courant-Weyl windows and the
+// trace always; 8 sampled columns of W (residual, Gram) when check_w; the same
+// columns of Q_out (Gram within tol_q) when check_q.  Raises ST_CHECK.
+hipError_t launch_debug_checks(const Work& w, bool check_w, bool check_q, double tol_q,
+                               hipStream_t s);
 
 // Launchers (stream-ordered, no allocation).
 hipError_t launch_qtk(const Work& w, hipStream_t s);

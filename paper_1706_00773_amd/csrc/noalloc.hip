@@ -46,9 +46,7 @@ int scratch_address(int dev, char** out) {
 
 // The sticky error bits of the update as an EIG_* code in the caller's word.
 __global__ void noalloc_status_kernel(const DevState* st, int32_t* out) {
-  const int b = st->status;
-  *out = (b & ST_NONFINITE) ? EIG_ENONFINITE : (b & ST_NOCONV) ? EIG_ENOCONV
-                                                               : (b ? EIG_EDEVICE : EIG_OK);
+  *out = status_code(st->status);
 }
 
 struct DeviceGuard {
@@ -104,6 +102,7 @@ extern "C" int eig_eigvals_rankk_noalloc(int64_t n, int64_t k, const double* lam
   w.k = (int)k;
   w.ldk = (int)ldk;
   w.ldq = (int)ldq;
+  w.max_evals = MAX_EVALS;
   w.sig_pos_mask = mask;
   w.ncols = (int)n;
   w.lam_in = lambda;

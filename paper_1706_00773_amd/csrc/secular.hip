@@ -612,7 +612,7 @@ __device__ __forceinline__ void rootsolve_body(const Work& w) {
           z.dprev = delta;
         }
         z.last_newton = !conv && (next != mid);
-        if (!conv && z.evals >= MAX_EVALS) {
+        if (!conv && z.evals >= w.max_evals) {
           conv = true;
           atomicOr(&w.st->status, ST_NOCONV);
         }

@@ -137,6 +137,7 @@ struct Matrix {
   int n = 0;
   size_t q_off = 0;  // arena offset of the current Q
   bool busy = false;
+  bool broken = false;  // an update failed; later ones are refused until a read
 };
 
 struct Slot {                  // one stream
@@ -180,12 +181,7 @@ double now_s(const eig_server_s* s) {
   return std::chrono::duration<double>(std::chrono::steady_clock::now() - s->t0).count();
 }
 
-int status_of(int bits) {
-  if (bits & ST_NONFINITE) return EIG_ENONFINITE;
-  if (bits & ST_NOCONV) return EIG_ENOCONV;
-  if (bits) return EIG_EDEVICE;
-  return EIG_OK;
-}
+int status_of(int bits) { return status_code(bits); }
 
 // Called with the lock held: finish the batch of slot i (its event has fired).
 void retire(eig_server_s* s, Slot& sl) {
@@ -202,6 +198,7 @@ void retire(eig_server_s* s, Slot& sl) {
       m.q_off = r->q_off;
     } else {
       if (rc == EIG_OK) rc = EIG_EDEVICE;
+      m.broken = true;
       s->arena.release(r->q_off, nn);
       // clear the sticky bits so that the matrix takes later updates; the copy
       // must have landed before any stream runs the matrix's next update
@@ -283,16 +280,26 @@ void fail_request(eig_server_s* s, Request* r, int rc) {
   s->cv_done.notify_all();
 }
 
-// Called with the lock held: admit what fits and launch it on slot `sl`.
-// Returns the number of updates launched (or -1 on a launch failure).
+// Called with the lock held: admit what fits and launch it on slot `sl`.  A
+// request of a matrix whose earlier update failed completes at once with
+// EIG_EDEPENDENCY.  Returns the number of requests launched or completed so
+// (or -1 on a launch failure).
 int launch(eig_server_s* s, Slot& sl) {
   std::vector<Request*> pick;
   std::vector<char> blocked(s->mats.size(), 0);  // head request waits for memory
   size_t kdoubles = 0;
   bool first = true;
+  int ndep = 0;
   for (auto it = s->pending.begin(); it != s->pending.end() && (int)pick.size() < s->max_batch;) {
     Request* r = *it;
     Matrix& m = s->mats[r->matrix];
+    if (!m.busy && m.broken) {
+      // its predecessor failed: not applied (the matrix keeps its state)
+      it = s->pending.erase(it);
+      fail_request(s, r, EIG_EDEPENDENCY);
+      ++ndep;
+      continue;
+    }
     const bool oldest = first;
     first = false;
     if (m.busy || blocked[r->matrix]) {
@@ -322,7 +329,7 @@ int launch(eig_server_s* s, Slot& sl) {
     pick.push_back(r);
     it = s->pending.erase(it);
   }
-  if (pick.empty()) return 0;
+  if (pick.empty()) return ndep;
   // stage the K matrices, build the items
   std::vector<eig_batch_item> items(pick.size());
   size_t o = 0;
@@ -374,7 +381,7 @@ int launch(eig_server_s* s, Slot& sl) {
   s->in_flight += (int)pick.size();
   s->batches += 1;
   s->batched_updates += (int64_t)pick.size();
-  return (int)pick.size();
+  return (int)pick.size() + ndep;
 }
 
 void worker_main(eig_server_s* s) {
@@ -642,6 +649,7 @@ int eig_server_read(eig_server_t s, int32_t matrix, double* lambda_out, double* 
     return true;
   });
   (void)hipSetDevice(s->device);
+  m.broken = false;  // the caller has seen the state a failed update left
   const int cur = (int)(m.st->enq_gen & 1);
   const hipMemcpyKind kind = ptrs_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
   if (lambda_out &&

@@ -37,7 +37,7 @@ def test_library_exports_every_declared_symbol():
 
 
 def test_status_strings():
-    for code in range(0, -10, -1):
+    for code in range(0, -11, -1):
         s = eu.eig_status_str(code)
         assert isinstance(s, str) and s and s != "unknown status"
     assert eu.eig_status_str(123) == "unknown status"

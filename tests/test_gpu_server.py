@@ -147,21 +147,76 @@ def test_admission_bounded_by_arena():
         assert e.value.code == eu.EIG_ENOMEM
 
 
-def test_failed_request_is_isolated():
+def _alone_sticky(lam, Q, updates):
+    """The matrix's updates applied with eig_update_rankk and no query between
+    them: a failed update leaves the state and turns the later ones into no-ops
+    until the final query (which reports the first failure)."""
+    import torch
+
+    n = lam.size
+    with eu.EigState(n, 0) as s:
+        s.upload(torch.from_numpy(lam).to("cuda:0"),
+                 torch.from_numpy(np.ascontiguousarray(Q.T)).to("cuda:0").t())
+        for K, sig in updates:
+            s.update(torch.from_numpy(np.ascontiguousarray(K.T)).to("cuda:0").t(), sig)
+        lo = torch.empty(n, dtype=torch.float64, device="cuda:0")
+        Qo = torch.empty((n, n), dtype=torch.float64, device="cuda:0").t()
+        try:
+            s.query(lo, Qo)
+        except eu.EigError:
+            s.query(lo, Qo)
+        return lo.cpu().numpy(), Qo.cpu().numpy()
+
+
+def test_failed_request_fails_its_dependents():
+    """A request with a NaN fails with EIG_ENONFINITE; the later requests of its
+    matrix complete with EIG_EDEPENDENCY unapplied (as later updates of a single
+    state are no-ops until its error is read); other matrices are untouched.
+    After eig_server_read of the matrix its requests are applied again."""
     print("case failed request in a stream", flush=True)
     sizes = [200, 150, 90]
     mats = _mats(sizes, 80)
     rng = np.random.default_rng(81)
     reqs = _requests(sizes, 30, rng, bad={5, 17})
-    comps, finals, stats = _serve(mats, reqs, arena=1 << 28)
-    st = {c["request_id"]: c["status"] for c in comps}
-    assert st[5] == eu.EIG_ENONFINITE and st[17] == eu.EIG_ENONFINITE
-    assert all(v == eu.EIG_OK for r, v in st.items() if r not in (5, 17))
-    assert stats["failed"] == 2
-    for m, (lam, Q) in enumerate(mats):
-        ups = [(K, sig) for rid, mm, K, sig in reqs if mm == m]
-        la, Qa = _alone(lam, Q, ups)
-        assert np.array_equal(finals[m][0], la) and np.array_equal(finals[m][1], Qa)
+    expect, broken = {}, set()
+    for rid, m, K, sig in reqs:
+        if m in broken:
+            expect[rid] = eu.EIG_EDEPENDENCY
+        elif rid in (5, 17):
+            expect[rid] = eu.EIG_ENONFINITE
+            broken.add(m)
+        else:
+            expect[rid] = eu.EIG_OK
+    with eu.EigServer(1 << 28, max_batch=8, streams=2) as srv:
+        for lam, Q in mats:
+            srv.add(lam, Q)
+        comps = []
+        for rid, m, K, sig in reqs:
+            srv.submit(m, K, sig, rid)
+            comps += srv.poll()
+        srv.drain()
+        comps += srv.poll()
+        st = {c["request_id"]: c["status"] for c in comps}
+        assert st == expect
+        assert srv.stats()["failed"] == sum(v != eu.EIG_OK for v in expect.values())
+        finals = [srv.read(m) for m in range(len(sizes))]
+        for m, (lam, Q) in enumerate(mats):
+            ups = [(K, sig) for rid, mm, K, sig in reqs if mm == m]
+            la, Qa = _alone_sticky(lam, Q, ups)
+            assert np.array_equal(finals[m][0], la) and np.array_equal(finals[m][1], Qa), m
+        # the read cleared the mark: one more request of a broken matrix applies
+        m = min(broken)
+        n = sizes[m]
+        K = np.asfortranarray(rng.standard_normal((n, 2)) / np.sqrt(n))
+        sig = np.array([1, -1], dtype=np.int8)
+        srv.submit(m, K, sig, 1000)
+        srv.drain()
+        last = srv.poll()
+        assert [c["status"] for c in last] == [eu.EIG_OK]
+        lf, Qf = srv.read(m)
+    good = [(K_, s_) for rid, mm, K_, s_ in reqs if mm == m and expect[rid] == eu.EIG_OK]
+    la, Qa = _alone(mats[m][0], mats[m][1], good + [(K, sig)])
+    assert np.array_equal(lf, la) and np.array_equal(Qf, Qa)
 
 
 def test_server_argument_errors():
