@@ -92,6 +92,11 @@ static void jacobi_sym(int m, double *a, double *w, double *V) {
     for (int r = 0; r < m; ++r)
       for (int c = 0; c < m; ++c) V[r * m + c] = (r == c) ? 1.0 : 0.0;
   }
+  /* Stop at a negligible off-diagonal, or once a sweep no longer reduces it:
+   * then the rotations only stir rounding errors (the off-diagonal has reached
+   * its floor, about eps ||a||), and further sweeps change nothing that
+   * matters. */
+  double off_prev = INFINITY;
   for (int sweep = 0; sweep < 100; ++sweep) {
     double off = 0.0, tot = 0.0;
     for (int r = 0; r < m; ++r)
@@ -100,7 +105,8 @@ static void jacobi_sym(int m, double *a, double *w, double *V) {
         tot += v;
         if (r != c) off += v;
       }
-    if (off == 0.0 || off <= 1e-36 * tot) break;
+    if (off == 0.0 || off <= 1e-36 * tot || !(off < off_prev)) break;
+    off_prev = off;
     for (int p = 0; p < m - 1; ++p)
       for (int q = p + 1; q < m; ++q) {
         double apq = a[p * m + q];
