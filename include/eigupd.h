@@ -162,7 +162,13 @@ enum {
                                2 k n^2 P / 256 doubles) on first use. */
 };
 
-enum { EIG_KMAX = 8 };
+/* Ranks: the kernels are specialised for 1 <= k <= EIG_KMAX.  eig_update_rankk
+ * also takes EIG_KMAX < k <= EIG_KMAX_GENERIC: the update is then applied as
+ * ceil(k / EIG_KMAX) successive updates of nearly equal rank (A + K Sigma K^T =
+ * (A + K_1 Sigma_1 K_1^T) + K_2 Sigma_2 K_2^T + ...; the paper's Sec. 3 compares
+ * exactly this split, two rank-1 updates, with one rank-2 update).  The other
+ * entry points take k <= EIG_KMAX. */
+enum { EIG_KMAX = 8, EIG_KMAX_GENERIC = 32 };
 
 /* Create a state for matrices of order n on HIP device `device`, and allocate
  * all its device memory: two copies of (lambda, Q) used alternately, the
@@ -193,7 +199,16 @@ int eig_state_upload(eig_state_t s, const double *lambda, const double *Q, int64
                      int32_t ptrs_on_device, void *hip_stream);
 
 /* Apply A' = A + K Sigma K^T to the resident decomposition (Sec. 2.1-2.4).
- *   k      rank, 1 <= k <= min(n, EIG_KMAX)
+ *   k      rank, 1 <= k <= min(n, EIG_KMAX_GENERIC).  For k > EIG_KMAX the
+ *          update runs as ceil(k / EIG_KMAX) chained parts; every part reads
+ *          the previous part's (lambda, Q), the committed pair is only read,
+ *          and the whole update commits at once (a device error in any part
+ *          leaves the state unchanged).  The first such update allocates one
+ *          more n-by-n buffer (8 n^2 bytes), kept until eig_state_destroy.
+ *          eig_info then describes the last part (its deflation, counts and
+ *          evaluations; p and q are the whole update's), eig_info.ms[0] also
+ *          holds the earlier parts, and eig_debug_fetch returns the last
+ *          part's intermediates (EIG_DBG_U: EIG_EINVAL).
  *   K      n-by-k column-major, leading dimension ldk >= n; a device pointer
  *          unless mode has EIG_HOST_INPUT
  *   sigma  host array of k entries, each +1 or -1
@@ -203,9 +218,10 @@ int eig_state_upload(eig_state_t s, const double *lambda, const double *Q, int64
  * Asynchronous: enqueues the kernels on `hip_stream` and returns.  On the
  * device the update writes the new pair into the state's other buffer and
  * commits it only if no error was raised; the state then holds A'.
- * Errors (synchronous): EIG_EINVAL, EIG_EUNSUPPORTED (k > EIG_KMAX, an
- * unknown mode bit, or precision selector 3), EIG_ENOMEM (slice planes of a
- * reduced mode could not be allocated),
+ * Errors (synchronous): EIG_EINVAL, EIG_EUNSUPPORTED (k > EIG_KMAX_GENERIC,
+ * an unknown mode bit, or precision selector 3), EIG_ENOMEM (slice planes of
+ * a reduced mode, the far-field buffers or the chained parts' buffer could not
+ * be allocated),
  * EIG_ESTATE (no upload yet), EIG_EDEVICE (launch failure).  Deferred:
  * EIG_ENONFINITE, EIG_ENOCONV, EIG_ECHECK (see the file header). */
 int eig_update_rankk(eig_state_t s, int64_t k, const double *K, int64_t ldk,

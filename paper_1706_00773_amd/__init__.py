@@ -44,6 +44,7 @@ EIG_PHASE_TIMING = 1 << 7
 EIG_LOCATE_RESIDUES = 1 << 8
 EIG_QW_FARFIELD = 1 << 9
 EIG_KMAX = 8
+EIG_KMAX_GENERIC = 32
 EIG_NOALLOC_NMAX = 16384
 
 EIG_DBG_U = 1

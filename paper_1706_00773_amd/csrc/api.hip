@@ -51,6 +51,7 @@ size_t carve(eig_state_s* s, void* base) {
   s->lam[0] = c.take<double>(n);
   s->lam[1] = c.take<double>(n);
   s->lam_vo = c.take<double>(n);
+  s->lam_x = c.take<double>(n);
   Work& w = s->w;
   if (s->lean) {
     // Q and W buffers are lent per update by the owner of the state
@@ -61,7 +62,7 @@ size_t carve(eig_state_s* s, void* base) {
     s->Q[1] = c.take<double>(n * n);
     w.W = c.take<double>(n * n);
   }
-  s->Kbuf = c.take<double>(n * KMAX);
+  s->Kbuf = c.take<double>(n * EIG_KMAX_GENERIC);
   c.off = carve_workspace(w, n, static_cast<char*>(base), c.off);
   w.lp_part = c.take<double>((size_t)LP_RESID_CHUNKS * n * KMAX);
   w.lp_resid = c.take<double>(n * KMAX);
@@ -133,6 +134,62 @@ hipError_t clear_status(DevState* dst, DevState ds, hipStream_t st) {
   hipError_t e = hipMemcpyAsync(dst, &ds, sizeof(ds), hipMemcpyHostToDevice, st);
   if (e == hipSuccess) e = hipStreamSynchronize(st);
   return e;
+}
+
+// Enqueues one update of rank w.k <= KMAX with the buffers in w: U = Q^T K,
+// deflation, location, roots, the merged eigenvalues, and (unless
+// values_only) W and Q_out = Q_in W; then the debug checks if asked.  Nothing
+// is committed.  mark(e) is called between the phases (e = 1..6, as in
+// eig_info.ms).
+template <typename Mark>
+int enqueue_part(eig_state_s* s, const Work& w, int prec, bool farfield, bool residues,
+                 bool checks, bool values_only, hipStream_t st, Mark&& mark) {
+  const int n = (int)s->n;
+  if (prec == EIG_GEMM_FP64)
+    HIPCHK(launch_qtk(w, st));
+  else
+    HIPCHK(launch_qtk_lp(w, prec, st));
+  HIPCHK(mark(1));
+  HIPCHK(launch_deflate(w, st));
+  HIPCHK(mark(2));
+  if (residues && w.k == 2) HIPCHK(launch_alpha_locate(w, st));
+  HIPCHK(launch_polecount(w, st));
+  HIPCHK(launch_locate(w, st));
+  HIPCHK(mark(3));
+  HIPCHK(launch_rootsolve(w, st));
+  HIPCHK(mark(4));
+  HIPCHK(launch_finalize(w, st));
+  if (values_only) {
+    if (checks) HIPCHK(launch_debug_checks(w, false, false, 0.0, st));
+    HIPCHK(mark(5));
+    HIPCHK(mark(6));
+    return EIG_OK;
+  }
+  const bool ff = farfield && ff_eligible(n, w.k);
+  const FarField f = ff ? ff_layout(s->ff_block, n, w.k) : FarField{};
+  if (ff) {
+    HIPCHK(launch_ff_plan(w, f, st));
+    HIPCHK(launch_wbuild_ff(w, f, st));
+  } else {
+    HIPCHK(launch_wbuild(w, st));
+  }
+  HIPCHK(launch_group_reflect(w, st));
+  HIPCHK(mark(5));
+  if (ff)
+    HIPCHK(launch_qw_farfield(w, f, st));
+  else if (prec == EIG_GEMM_FP64)
+    HIPCHK(launch_dgemm(n, n, n, w.Q_in, n, w.W, n, w.Q_out, n, &w.st->status, st));
+  else
+    HIPCHK(launch_gemm_lp(w, prec, s->lp_block, static_cast<char*>(s->lp_block) + s->lp_bytes / 2,
+                          st));
+  HIPCHK(mark(6));
+  if (checks) {
+    // W is whole unless the far-field product formed only its near blocks; the
+    // reduced products' bound on Q'^T Q' - I is 2 sqrt(n) 4e-6
+    const double tol_q = (prec == EIG_GEMM_FP64) ? 1e-9 : 8e-6 * std::sqrt((double)n);
+    HIPCHK(launch_debug_checks(w, !ff, true, tol_q, st));
+  }
+  return EIG_OK;
 }
 
 }  // namespace
@@ -223,6 +280,7 @@ int eig_state_destroy(eig_state_t s) {
     if (s->block) (void)hipFree(s->block);
     if (s->lp_block) (void)hipFree(s->lp_block);
     if (s->ff_block) (void)hipFree(s->ff_block);
+    if (s->Q_x) (void)hipFree(s->Q_x);
   }
   delete s;
   return EIG_OK;
@@ -274,18 +332,18 @@ int eig_state_upload(eig_state_t s, const double* lambda, const double* Q, int64
 int eig_update_rankk(eig_state_t s, int64_t k, const double* K, int64_t ldk, const int8_t* sigma,
                      uint32_t mode, void* hip_stream) {
   if (!s || !K || !sigma || k < 1 || ldk < s->n || s->lean) return EIG_EINVAL;
-  if (k > EIG_KMAX) return EIG_EUNSUPPORTED;
-  if (k > s->n) return EIG_EINVAL;
+  if (k > EIG_KMAX_GENERIC) return EIG_EUNSUPPORTED;
+  if (k > s->n || ldk > INT32_MAX) return EIG_EINVAL;
   const uint32_t known = EIG_GEMM_MASK | EIG_VALUES_ONLY | EIG_HOST_INPUT | EIG_PHASE_TIMING |
                          EIG_LOCATE_RESIDUES | EIG_QW_FARFIELD | EIG_DEBUG_CHECKS;
   if (mode & ~known) return EIG_EUNSUPPORTED;
   const int prec = (int)(mode & EIG_GEMM_MASK);
   if (prec != EIG_GEMM_FP64 && prec != EIG_GEMM_FP32_CORR && prec != EIG_GEMM_BF16X3_CORR)
     return EIG_EUNSUPPORTED;
-  int mask = 0;
+  int npos = 0;
   for (int64_t c = 0; c < k; ++c) {
     if (sigma[c] == 1)
-      mask |= 1 << c;
+      ++npos;
     else if (sigma[c] != -1)
       return EIG_EINVAL;
   }
@@ -294,127 +352,103 @@ int eig_update_rankk(eig_state_t s, int64_t k, const double* K, int64_t ldk, con
   if (!g.ok) return EIG_EDEVICE;
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
   const size_t n = (size_t)s->n;
-  Work w = s->w;
-  w.k = (int)k;
-  w.sig_pos_mask = mask;
+  const bool vo = (mode & EIG_VALUES_ONLY) != 0;
+  // ranks above EIG_KMAX: ceil(k / EIG_KMAX) parts of nearly equal rank, applied in turn
+  const int parts = (int)((k + EIG_KMAX - 1) / EIG_KMAX);
+  const int part_k = (int)((k + parts - 1) / parts);  // the largest part
+  const double* Kd = K;
+  int64_t ldkd = ldk;
   if (mode & EIG_HOST_INPUT) {
     HIPCHK(hipMemcpy2DAsync(s->Kbuf, n * sizeof(double), K, (size_t)ldk * sizeof(double),
                             n * sizeof(double), (size_t)k, hipMemcpyHostToDevice, st));
     HIPCHK(hipStreamSynchronize(st));
-    w.K = s->Kbuf;
-    w.ldk = (int)n;
-  } else {
-    w.K = K;
-    w.ldk = (int)ldk;
+    Kd = s->Kbuf;
+    ldkd = (int64_t)n;
   }
-  const int cur = (int)(s->enq_gen & 1);
-  w.lam_in = s->lam[cur];
-  w.Q_in = s->Q[cur];
-  w.lam_out = s->lam[cur ^ 1];
-  w.Q_out = s->Q[cur ^ 1];
-  const bool timed = (mode & EIG_PHASE_TIMING) != 0;
-  auto mark = [&](int i) -> hipError_t {
-    return timed ? hipEventRecord(s->ev[i], st) : hipSuccess;
-  };
-  const bool vo = (mode & EIG_VALUES_ONLY) != 0;
-  if (prec != EIG_GEMM_FP64 && !vo) {
-    // slice planes of Q and W for the matrix-core product, kept for later updates
-    const size_t need = 2 * lp_plane_bytes(prec, (int)n);
-    if (s->lp_bytes < need) {
-      if (s->lp_block) {
-        HIPCHK(hipStreamSynchronize(st));
-        HIPCHK(hipDeviceSynchronize());
-        (void)hipFree(s->lp_block);
-        s->lp_block = nullptr;
-        s->lp_bytes = 0;
-      }
-      if (hipMalloc(&s->lp_block, need) != hipSuccess) {
-        (void)hipGetLastError();
-        s->lp_block = nullptr;
-        return EIG_ENOMEM;
-      }
-      s->lp_bytes = need;
+  // buffers allocated on first use: slice planes of the reduced modes, the
+  // far-field product's expansions, and a second Q for the chained parts
+  auto grow = [&](void** blk, size_t* have, size_t need) -> int {
+    if (*have >= need) return EIG_OK;
+    if (*blk) {
+      HIPCHK(hipStreamSynchronize(st));
+      HIPCHK(hipDeviceSynchronize());
+      (void)hipFree(*blk);
+      *blk = nullptr;
+      *have = 0;
     }
-  }
-  const bool farfield = (mode & EIG_QW_FARFIELD) && prec == EIG_GEMM_FP64 && !vo &&
-                        ff_eligible((int)n, (int)k);
-  if (farfield) {
-    const size_t need = ff_bytes((int)n, (int)k);
-    if (s->ff_bytes < need) {
-      if (s->ff_block) {
-        HIPCHK(hipStreamSynchronize(st));
-        HIPCHK(hipDeviceSynchronize());
-        (void)hipFree(s->ff_block);
-        s->ff_block = nullptr;
-        s->ff_bytes = 0;
-      }
-      if (hipMalloc(&s->ff_block, need) != hipSuccess) {
-        (void)hipGetLastError();
-        s->ff_block = nullptr;
-        return EIG_ENOMEM;
-      }
-      s->ff_bytes = need;
+    if (hipMalloc(blk, need) != hipSuccess) {
+      (void)hipGetLastError();
+      *blk = nullptr;
+      return EIG_ENOMEM;
     }
-  }
-  HIPCHK(mark(0));
-  if (prec == EIG_GEMM_FP64)
-    HIPCHK(launch_qtk(w, st));
-  else
-    HIPCHK(launch_qtk_lp(w, prec, st));
-  HIPCHK(mark(1));
-  HIPCHK(launch_deflate(w, st));
-  HIPCHK(mark(2));
-  if ((mode & EIG_LOCATE_RESIDUES) && k == 2) HIPCHK(launch_alpha_locate(w, st));
-  HIPCHK(launch_polecount(w, st));
-  HIPCHK(launch_locate(w, st));
-  HIPCHK(mark(3));
-  HIPCHK(launch_rootsolve(w, st));
-  HIPCHK(mark(4));
-  s->last_k = (int)k;
-  s->timed = timed;
-  const bool checks = (mode & EIG_DEBUG_CHECKS) != 0;
-  if (vo) {
-    w.lam_fin = s->lam_vo;
-    HIPCHK(launch_finalize(w, st));
-    if (checks) HIPCHK(launch_debug_checks(w, false, false, 0.0, st));
-    HIPCHK(mark(5));
-    HIPCHK(mark(6));
-    HIPCHK(mark(7));
-    HIPCHK(mark(8));
-    s->last_vo = true;
+    *have = need;
     return EIG_OK;
+  };
+  const bool any_product = !vo || parts > 1;
+  if (prec != EIG_GEMM_FP64 && any_product) {
+    const int rc = grow(&s->lp_block, &s->lp_bytes, 2 * lp_plane_bytes(prec, (int)n));
+    if (rc != EIG_OK) return rc;
   }
-  w.lam_fin = w.lam_out;
-  HIPCHK(launch_finalize(w, st));
-  const FarField ff = farfield ? ff_layout(s->ff_block, (int)n, (int)k) : FarField{};
+  const bool farfield = (mode & EIG_QW_FARFIELD) && prec == EIG_GEMM_FP64 && any_product &&
+                        ff_eligible((int)n, part_k);
   if (farfield) {
-    HIPCHK(launch_ff_plan(w, ff, st));
-    HIPCHK(launch_wbuild_ff(w, ff, st));
-  } else {
-    HIPCHK(launch_wbuild(w, st));
+    const int rc = grow(&s->ff_block, &s->ff_bytes, ff_bytes((int)n, part_k));
+    if (rc != EIG_OK) return rc;
   }
-  HIPCHK(launch_group_reflect(w, st));
-  HIPCHK(mark(5));
-  if (farfield)
-    HIPCHK(launch_qw_farfield(w, ff, st));
-  else if (prec == EIG_GEMM_FP64)
-    HIPCHK(launch_dgemm((int)n, (int)n, (int)n, w.Q_in, (int)n, w.W, (int)n, w.Q_out, (int)n,
-                        &w.st->status, st));
-  else
-    HIPCHK(launch_gemm_lp(w, prec, s->lp_block,
-                          static_cast<char*>(s->lp_block) + s->lp_bytes / 2, st));
-  HIPCHK(mark(6));
-  if (checks) {
-    // W is whole unless the far-field product formed only its near blocks; the
-    // reduced products' bound on Q'^T Q' - I is 2 sqrt(n) 4e-6
-    const double tol_q = (prec == EIG_GEMM_FP64) ? 1e-9 : 8e-6 * std::sqrt((double)n);
-    HIPCHK(launch_debug_checks(w, !farfield, true, tol_q, st));
+  if (parts > 1 && !s->Q_x) {
+    void* q = nullptr;
+    size_t have = 0;
+    const int rc = grow(&q, &have, n * n * sizeof(double));
+    if (rc != EIG_OK) return rc;
+    s->Q_x = static_cast<double*>(q);
   }
-  HIPCHK(launch_commit(w, st));
-  HIPCHK(mark(7));
-  HIPCHK(mark(8));
-  s->enq_gen += 1;
-  s->last_vo = false;
+  const bool timed = (mode & EIG_PHASE_TIMING) != 0;
+  const bool checks = (mode & EIG_DEBUG_CHECKS) != 0;
+  const int cur = (int)(s->enq_gen & 1);
+  double* lam_final = vo ? s->lam_vo : s->lam[cur ^ 1];
+  Work w = s->w;
+  if (timed) HIPCHK(hipEventRecord(s->ev[0], st));
+  int c0 = 0;
+  for (int i = 0; i < parts; ++i) {
+    const int kc = (int)(k / parts) + (i < (int)(k % parts) ? 1 : 0);
+    const bool last = (i == parts - 1);
+    // the last part writes the state's other buffers, the one before it the
+    // spare ones, and so on back: no part writes what it reads, and the
+    // committed (lambda, Q) is read but never written
+    const bool to_final = ((parts - 1 - i) % 2) == 0;
+    int mask = 0;
+    for (int c = 0; c < kc; ++c) mask |= (sigma[c0 + c] == 1) ? (1 << c) : 0;
+    const double* lam_in = (i == 0) ? s->lam[cur] : w.lam_fin;
+    const double* Q_in = (i == 0) ? s->Q[cur] : w.Q_out;
+    w = s->w;
+    w.k = kc;
+    w.sig_pos_mask = mask;
+    w.K = Kd + (size_t)c0 * ldkd;
+    w.ldk = (int)ldkd;
+    w.lam_in = lam_in;
+    w.Q_in = Q_in;
+    w.lam_out = to_final ? s->lam[cur ^ 1] : s->lam_x;
+    w.lam_fin = to_final ? lam_final : s->lam_x;
+    w.Q_out = to_final ? s->Q[cur ^ 1] : s->Q_x;
+    auto mark = [&](int e) -> hipError_t {
+      return (timed && last && e > 0) ? hipEventRecord(s->ev[e], st) : hipSuccess;
+    };
+    const int rc = enqueue_part(s, w, prec, farfield, (mode & EIG_LOCATE_RESIDUES) != 0, checks,
+                                vo && last, st, mark);
+    if (rc != EIG_OK) return rc;
+    c0 += kc;
+  }
+  s->last_k = (int)k;
+  s->last_p = npos;
+  s->last_q = (int)k - npos;
+  s->timed = timed;
+  if (!vo) HIPCHK(launch_commit(w, st));
+  if (timed) {
+    HIPCHK(hipEventRecord(s->ev[7], st));
+    HIPCHK(hipEventRecord(s->ev[8], st));
+  }
+  if (!vo) s->enq_gen += 1;
+  s->last_vo = vo;
   return EIG_OK;
 }
 
@@ -475,6 +509,8 @@ int eig_update_interval(eig_state_t s, int64_t k, const double* K, int64_t ldk,
   *m_out = m;
   if (m > m_max) return EIG_EINVAL;
   s->last_k = (int)k;
+  s->last_p = __builtin_popcount((unsigned)mask);
+  s->last_q = (int)k - s->last_p;
   if (m == 0) return EIG_OK;
   // phase 2: those roots, their vectors, W (n x m) and V = Q W (2 n^2 m flops)
   w.lam_fin = lambda_out;
@@ -570,6 +606,8 @@ int eig_sturm_chain(eig_state_t s, int64_t k, const double* K, int64_t ldk,
   info->n_deflated = (int64_t)n - n_d;
   info->reserved = 0;
   s->last_k = (int)k;
+  s->last_p = __builtin_popcount((unsigned)mask);
+  s->last_q = (int)k - s->last_p;
   return EIG_OK;
 }
 
@@ -647,8 +685,8 @@ int eig_query(eig_state_t s, double* lambda_out, double* Q_out, int64_t ldq,
     info->n = s->n;
     info->k = s->last_k;
     if (s->last_k > 0) {
-      info->p = di.p;
-      info->q = di.q;
+      info->p = s->last_p;
+      info->q = s->last_q;
       info->n_deflated_rows = di.n_defl;
       info->n_deflated_groups = di.n_groups;
       info->n_segments = di.n_s;
@@ -685,7 +723,11 @@ int eig_debug_fetch(eig_state_t s, int32_t what, void* dst, int64_t bytes, void*
   const void* src = nullptr;
   size_t need = 0;
   switch (what) {
-    case EIG_DBG_U: src = w.U; need = n * (size_t)s->last_k * sizeof(double); break;
+    case EIG_DBG_U:
+      if (s->last_k > EIG_KMAX) return EIG_EINVAL;  // a chained update keeps only its last part
+      src = w.U;
+      need = n * (size_t)s->last_k * sizeof(double);
+      break;
     case EIG_DBG_POLE_COUNT: src = w.nu; need = (size_t)di.n_s * sizeof(int); break;
     case EIG_DBG_SEG_START: src = w.seg_start; need = (size_t)(di.n_s + 1) * sizeof(int); break;
     case EIG_DBG_REDUCED_D: src = w.rd; need = (size_t)di.n_d * sizeof(double); break;

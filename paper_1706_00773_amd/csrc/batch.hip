@@ -456,6 +456,8 @@ int eig_update_batch(eig_batch_t b, const eig_batch_item* items, int32_t count, 
   for (int i = 0; i < count; ++i) {
     eig_state_s* s = items[i].state;
     s->last_k = (int)items[i].k;
+    s->last_p = __builtin_popcount((unsigned)masks[i]);
+    s->last_q = s->last_k - s->last_p;
     s->timed = false;
     s->last_vo = vo;
     if (!vo) s->enq_gen += 1;

@@ -14,11 +14,13 @@ struct eig_state_s {
   double* lam[2] = {nullptr, nullptr};
   double* Q[2] = {nullptr, nullptr};
   double* lam_vo = nullptr;
-  double* Kbuf = nullptr;
+  double* lam_x = nullptr;   // eigenvalues between the chained parts of a rank > 8 update
+  double* Kbuf = nullptr;    // n x EIG_KMAX_GENERIC: host K of EIG_HOST_INPUT
   void* lp_block = nullptr;  // slice planes of the reduced-precision modes (lazily)
   size_t lp_bytes = 0;
   void* ff_block = nullptr;  // buffers of the far-field product (lazily)
   size_t ff_bytes = 0;
+  double* Q_x = nullptr;     // n x n: Q between the chained parts of a rank > 8 update (lazily)
   eigupd::Work w{};       // workspace pointers (carved from block)
   hipEvent_t ev[9] = {};  // phase events (EIG_PHASE_TIMING)
   bool timed = false;
@@ -26,6 +28,7 @@ struct eig_state_s {
   bool uploaded = false;  // a decomposition has been uploaded
   bool last_vo = false;   // the last update was values-only
   int last_k = 0;         // rank of the last update
+  int last_p = 0, last_q = 0;  // its numbers of sigma_c = +1 and -1
 };
 
 namespace eigupd {

@@ -333,9 +333,9 @@ def test_argument_errors():
         with pytest.raises(eu.EigError) as e:
             s.update(colmajor(u.K, dev), np.array([1, 0]))
         assert e.value.code == eu.EIG_EINVAL
-        K9 = np.zeros((n, 9), order="F")
+        K33 = np.zeros((n, 33), order="F")
         with pytest.raises(eu.EigError) as e:
-            s.update(colmajor(K9, dev), np.ones(9))
+            s.update(colmajor(K33, dev), np.ones(33))
         assert e.value.code == eu.EIG_EUNSUPPORTED
 
 
