@@ -154,9 +154,8 @@ enum {
                                product on the device when the update merged
                                equal poles; ignored for n < 2048, for
                                n >= 2049 * 256 and with the
-                               reduced-precision modes; single updates only
-                               (eig_update_batch returns EIG_EUNSUPPORTED for
-                               it).  Only the blocks of W
+                               reduced-precision modes; batches take it too
+                               (eig_update_batch).  Only the blocks of W
                                it reads are formed (the debug copy of W is then
                                partial).  Allocates its buffers (about
                                2 k n^2 P / 256 doubles) on first use. */
@@ -358,7 +357,12 @@ int eig_batch_create(eig_batch_t *out, int32_t max_items, int32_t device);
 /* Enqueue one update per item on hip_stream (asynchronous, like
  * eig_update_rankk; K borrowed until the stream reaches the batch).  mode:
  * EIG_GEMM_FP64, optionally | EIG_VALUES_ONLY (then nothing is committed and
- * eig_query returns the values, as for a single update).  A shape -- the
+ * eig_query returns the values, as for a single update) or | EIG_QW_FARFIELD
+ * (items with n >= 2048 form Q' by the far-field product, with launches of
+ * their own, bitwise as a single update in that mode; the first such update
+ * of a state allocates its far-field buffers, sized for rank EIG_KMAX; a
+ * batch with such items is launched directly, never replayed as a graph).
+ * A shape -- the
  * ordered (k, n) list and the mode -- is tuned on its first two calls (those
  * two synchronise the stream) and captured into a HIP graph on its next call;
  * later calls with that shape replay the graph.  Calls on one batch context
@@ -366,7 +370,8 @@ int eig_batch_create(eig_batch_t *out, int32_t max_items, int32_t device);
  * that state, reported by its eig_query); the other states commit.
  * Errors (synchronous, nothing enqueued): EIG_EINVAL (bad item, a state twice,
  * count out of range, a state on another device), EIG_ESTATE (a state not
- * uploaded), EIG_EUNSUPPORTED (k > EIG_KMAX or other mode bits), EIG_EDEVICE. */
+ * uploaded), EIG_EUNSUPPORTED (k > EIG_KMAX or other mode bits), EIG_ENOMEM (the
+ * far-field buffers), EIG_EDEVICE. */
 int eig_update_batch(eig_batch_t b, const eig_batch_item *items, int32_t count, uint32_t mode,
                      void *hip_stream);
 
@@ -408,6 +413,11 @@ int eig_batch_destroy(eig_batch_t b);
  * EIG_EDEPENDENCY without being applied until eig_server_read of that matrix:
  * an update is never applied to a decomposition other than the one its
  * predecessors were meant to produce.
+ *
+ * Products: batches run with EIG_QW_FARFIELD, so matrices with n >= 2048 form
+ * Q' by the far-field product; its buffers (about 2 EIG_KMAX n^2 24 / 256
+ * doubles per such matrix) are allocated outside the arena on the matrix's
+ * first update and kept.
  *
  * Memory: one device arena of arena_bytes holds every n x n buffer.  A
  * resident matrix keeps its current Q there (8 n^2 bytes; lambda and O(n k)

@@ -54,6 +54,10 @@ struct Plan {
   size_t gemm_bytes_off = 0, prefix_bytes_off = 0, bytes = 0;
   int gemm_blocks = 0;
   int count = 0;
+  std::vector<char> ff;       // per position: Q' = Q W by the far-field product
+  std::vector<Work> host_works;  // per position (the far-field launches take them by value)
+  std::vector<eig_state_s*> states;  // per position
+  bool any_ff = false;
   std::string key;            // shape: mode, then (k, n) per position
 };
 
@@ -174,6 +178,18 @@ hipError_t enqueue(eig_batch_s* b, const Plan& p, bool vo, int root_form, int ti
     if (p.cnt[k]) STEP(launch_reflect_group(k, group(k, KIND_REFL), p.blocks[k][KIND_REFL], st));
   if (ev) STEP(hipEventRecord(ev[2], st));
   STEP(launch_dgemm_group(tile, d_gemm, d_prefix + p.gemm_poff, p.count, p.gemm_blocks, st));
+  // instances of the far-field product: their own plan, W blocks and products
+  // (the grouped launches above gave them no blocks)
+  for (int pos = 0; pos < p.count; ++pos) {
+    if (!p.ff[pos]) continue;
+    const Work& w = p.host_works[pos];
+    eig_state_s* s = p.states[pos];
+    const FarField f = ff_layout(s->ff_block, w.n, w.k);
+    STEP(launch_ff_plan(w, f, st));
+    STEP(launch_wbuild_ff(w, f, st));
+    STEP(launch_group_reflect(w, st));
+    STEP(launch_qw_farfield(w, f, st));
+  }
   if (ev) STEP(hipEventRecord(ev[3], st));
   STEP(launch_commit_group(d_works, p.count, st));
 #undef STEP
@@ -283,8 +299,9 @@ int eig_batch_get(eig_batch_t b, int32_t knob, int64_t* value) {
 int eig_update_batch(eig_batch_t b, const eig_batch_item* items, int32_t count, uint32_t mode,
                      void* hip_stream) {
   if (!b || !items || count < 1 || count > b->max_items) return EIG_EINVAL;
-  if (mode & ~(uint32_t)EIG_VALUES_ONLY) return EIG_EUNSUPPORTED;
+  if (mode & ~(uint32_t)(EIG_VALUES_ONLY | EIG_QW_FARFIELD)) return EIG_EUNSUPPORTED;
   const bool vo = (mode & EIG_VALUES_ONLY) != 0;
+  const bool want_ff = (mode & EIG_QW_FARFIELD) && !vo;
   // argument checks (nothing is enqueued if one fails)
   std::vector<int> masks(count);
   for (int i = 0; i < count; ++i) {
@@ -324,7 +341,7 @@ int eig_update_batch(eig_batch_t b, const eig_batch_item* items, int32_t count, 
     p.off[k] = acc;
     acc += p.cnt[k];
   }
-  p.key = vo ? "v" : "f";
+  p.key = vo ? "v" : (want_ff ? "F" : "f");
   char buf[48];
   for (int pos = 0; pos < count; ++pos) {
     const eig_batch_item& it = items[p.order[pos]];
@@ -348,6 +365,34 @@ int eig_update_batch(eig_batch_t b, const eig_batch_item* items, int32_t count, 
   if (b->force_tile != EIG_AUTO) tile = b->force_tile;
   if (b->force_root != EIG_AUTO && (vo || b->force_tile != EIG_AUTO)) measuring = false;
 
+  // far-field instances: their buffers (sized for rank EIG_KMAX, so that later
+  // batches of other ranks do not reallocate them), allocated on first use
+  p.ff.assign(count, 0);
+  p.host_works.resize(count);
+  p.states.resize(count);
+  for (int pos = 0; pos < count; ++pos) {
+    const eig_batch_item& it = items[p.order[pos]];
+    eig_state_s* s = it.state;
+    if (!want_ff || !ff_eligible((int)s->n, (int)it.k)) continue;
+    const size_t need = ff_bytes((int)s->n, KMAX);
+    if (s->ff_bytes < need) {
+      if (s->ff_block) {
+        HIPCHK(hipDeviceSynchronize());
+        (void)hipFree(s->ff_block);
+        s->ff_block = nullptr;
+        s->ff_bytes = 0;
+      }
+      if (hipMalloc(&s->ff_block, need) != hipSuccess) {
+        (void)hipGetLastError();
+        s->ff_block = nullptr;
+        return EIG_ENOMEM;
+      }
+      s->ff_bytes = need;
+    }
+    p.ff[pos] = 1;
+    p.any_ff = true;
+  }
+
   // per-call descriptors into a pinned slot
   layout(p);
   const int sl = b->slot;
@@ -363,9 +408,12 @@ int eig_update_batch(eig_batch_t b, const eig_batch_item* items, int32_t count, 
     eig_state_s* s = it.state;
     const int k = (int)it.k, n = (int)s->n;
     hw[pos] = make_work(s, k, it.K, (int)it.ldk, masks[p.order[pos]], vo);
+    p.host_works[pos] = hw[pos];
+    p.states[pos] = s;
     const int local = pos - p.off[k];
-    const int nb[NKIND] = {qtk_blocks(n, k), root_blocks(n), wbuild_blocks(n), reflect_blocks(n),
-                           solve_blocks(n)};
+    const bool ff = p.ff[pos] != 0;  // W and Q' by its own far-field launches
+    const int nb[NKIND] = {qtk_blocks(n, k), root_blocks(n), ff ? 0 : wbuild_blocks(n),
+                           ff ? 0 : reflect_blocks(n), solve_blocks(n)};
     for (int kind = 0; kind < NKIND; ++kind) {
       int* pre = hp + p.poff[k][kind];
       pre[local] = run[k][kind];
@@ -388,7 +436,7 @@ int eig_update_batch(eig_batch_t b, const eig_batch_item* items, int32_t count, 
     d.n = w.n;
     d.vec = !(w.n & 1);
     hg[pos] = d;
-    gp[pos + 1] = gp[pos] + gemm_tiles(w.n, tile);
+    gp[pos + 1] = gp[pos] + (p.ff[pos] ? 0 : gemm_tiles(w.n, tile));
   }
   p.gemm_blocks = gp[count];
   HIPCHK(hipMemcpyAsync(b->d_block, h, p.bytes, hipMemcpyHostToDevice, st));
@@ -412,7 +460,10 @@ int eig_update_batch(eig_batch_t b, const eig_batch_item* items, int32_t count, 
       tu.tile = (!vo && tu.gemm_ms[1] < tu.gemm_ms[0]) ? 64 : 128;
       tu.done = true;
     }
-  } else if (b->use_graphs) {
+  } else if (b->use_graphs && !p.any_ff) {
+    // (a batch with far-field instances is launched directly: its far-field
+    // launches take each state's buffers as arguments, which a replay for other
+    // states of the same shape would reuse)
     snprintf(buf, sizeof buf, "#%d,%d", root_form, tile);
     const std::string gkey = p.key + buf;
     eig_batch_s::Entry& en = b->graphs[gkey];

@@ -20,6 +20,11 @@
 // matrices are independent and are batched together, up to max_batch per
 // batch, oldest first.
 //
+// Products.  Batches run with EIG_QW_FARFIELD: matrices with n >= 2048 form
+// Q' = Q W by the far-field product (its buffers, outside the arena, are
+// allocated on the matrix's first update and kept), the others by the grouped
+// dense product.
+//
 // Streams.  Each of the server's streams has its own batch context (fixed
 // knobs: persistent root solver, no graphs -- the batch shapes of a request
 // stream rarely repeat), pinned staging for the batch's K matrices and a
@@ -354,7 +359,8 @@ int launch(eig_server_s* s, Slot& sl) {
   hipError_t e = hipMemcpyAsync(sl.d_K, sl.h_K, o * sizeof(double), hipMemcpyHostToDevice,
                                 sl.stream);
   int rc = (e == hipSuccess)
-               ? eig_update_batch(sl.batch, items.data(), (int32_t)items.size(), 0, sl.stream)
+               ? eig_update_batch(sl.batch, items.data(), (int32_t)items.size(), EIG_QW_FARFIELD,
+                                  sl.stream)
                : EIG_EDEVICE;
   if (rc == EIG_OK) {
     for (size_t i = 0; i < pick.size(); ++i) {

@@ -225,3 +225,61 @@ def test_batch_argument_errors():
         # nothing was enqueued: both states are still at generation 0
         assert a0.query().generation == 0 and a1.query().generation == 0
     _close(insts)
+
+
+def _state(u):
+    import torch
+
+    s = eu.EigState(u.lam.size, 0)
+    s.upload(torch.from_numpy(u.lam).to("cuda:0"), _dev_colmajor(u.Q))
+    return s
+
+
+def test_farfield_batch_matches_single_updates():
+    """EIG_QW_FARFIELD in a batch: the instances with n >= 2048 form Q' with
+    their own far-field launches, the others with the grouped dense product;
+    every state ends bitwise where the same updates with the same mode, one at
+    a time, leave it (three chained batches, no graph replay)."""
+    import torch
+
+    shapes = [(2048, 2), (300, 2), (3000, 4), (2500, 8), (700, 4)]
+    print(f"case far-field batch: {shapes}", flush=True)
+    rng = np.random.default_rng(2048)
+    us = []
+    for i, (n, k) in enumerate(shapes):
+        lam = wl.distinct_uniform(n, -1.0, 1.0, 1e-12, rng)
+        Q = wl.orthogonal_from(wl.gaussian_square(n, rng), "cuda:0")
+
+        class U:
+            pass
+
+        u = U()
+        u.lam, u.Q = lam, Q
+        us.append(u)
+    bstates = [eu.EigState(u.lam.size, 0) for u in us]
+    sstates = [eu.EigState(u.lam.size, 0) for u in us]
+    for u, a, b in zip(us, bstates, sstates):
+        a.upload(torch.from_numpy(u.lam).to("cuda:0"), u.Q)
+        b.upload(torch.from_numpy(u.lam).to("cuda:0"), u.Q)
+    with eu.EigBatch(8) as batch:
+        for step in range(3):
+            perts = _perturbations(shapes, rng)
+            batch.update([(a, K, sig) for a, (K, sig, _) in zip(bstates, perts)],
+                         eu.EIG_QW_FARFIELD)
+            for b, (K, sig, _) in zip(sstates, perts):
+                b.update(K, sig, eu.EIG_QW_FARFIELD)
+            assert batch.get(eu.EIG_KNOB_GRAPHS) == 0
+    for (n, k), a, b in zip(shapes, bstates, sstates):
+        la = torch.empty(n, dtype=torch.float64, device="cuda:0")
+        Qa = torch.empty((n, n), dtype=torch.float64, device="cuda:0").t()
+        lb, Qb = torch.empty_like(la), torch.empty((n, n), dtype=torch.float64,
+                                                   device="cuda:0").t()
+        ia = a.query(la, Qa)
+        b.query(lb, Qb)
+        assert ia.generation == 3
+        assert torch.equal(la, lb) and torch.equal(Qa, Qb), (n, k)
+        G = Qa.t() @ Qa
+        G.diagonal().sub_(1.0)
+        assert float(G.abs().max()) <= 1e-9
+        a.close()
+        b.close()

@@ -4,7 +4,8 @@ The key property: a request's result is the same alone and in the mix.  Every
 matrix's requests, submitted interleaved with other matrices' requests (and
 with submissions spread over time, so batches form while others run), must
 leave that matrix bitwise where the same updates applied alone, one by one,
-with eig_update_rankk leave it (batched kernels compute the same numbers as
+with eig_update_rankk in the server's mode (EIG_QW_FARFIELD: the far-field
+product for n >= 2048) leave it (batched kernels compute the same numbers as
 single ones); the final eigenvalues are also checked against the oracle
 chained over the same updates, within the FP64 bar.  Admission by memory,
 per-request failures and the completion records are checked too.
@@ -61,7 +62,8 @@ def _alone(lam, Q, updates):
         s.upload(torch.from_numpy(lam).to("cuda:0"),
                  torch.from_numpy(np.ascontiguousarray(Q.T)).to("cuda:0").t())
         for K, sig in updates:
-            s.update(torch.from_numpy(np.ascontiguousarray(K.T)).to("cuda:0").t(), sig)
+            s.update(torch.from_numpy(np.ascontiguousarray(K.T)).to("cuda:0").t(), sig,
+                     eu.EIG_QW_FARFIELD)  # the server's mode (n >= 2048: far-field)
             try:
                 s.query()
             except eu.EigError:
@@ -158,7 +160,8 @@ def _alone_sticky(lam, Q, updates):
         s.upload(torch.from_numpy(lam).to("cuda:0"),
                  torch.from_numpy(np.ascontiguousarray(Q.T)).to("cuda:0").t())
         for K, sig in updates:
-            s.update(torch.from_numpy(np.ascontiguousarray(K.T)).to("cuda:0").t(), sig)
+            s.update(torch.from_numpy(np.ascontiguousarray(K.T)).to("cuda:0").t(), sig,
+                     eu.EIG_QW_FARFIELD)
         lo = torch.empty(n, dtype=torch.float64, device="cuda:0")
         Qo = torch.empty((n, n), dtype=torch.float64, device="cuda:0").t()
         try:
