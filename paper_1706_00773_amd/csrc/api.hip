@@ -13,6 +13,7 @@
 #include "eigupd.h"
 #include "internal.h"
 #include "state.h"
+#include "trace.h"
 
 using namespace eigupd;
 
@@ -145,45 +146,70 @@ template <typename Mark>
 int enqueue_part(eig_state_s* s, const Work& w, int prec, bool farfield, bool residues,
                  bool checks, bool values_only, hipStream_t st, Mark&& mark) {
   const int n = (int)s->n;
-  if (prec == EIG_GEMM_FP64)
-    HIPCHK(launch_qtk(w, st));
-  else
-    HIPCHK(launch_qtk_lp(w, prec, st));
+  {
+    TraceRange r("eig.qtk");
+    if (prec == EIG_GEMM_FP64)
+      HIPCHK(launch_qtk(w, st));
+    else
+      HIPCHK(launch_qtk_lp(w, prec, st));
+  }
   HIPCHK(mark(1));
-  HIPCHK(launch_deflate(w, st));
+  {
+    TraceRange r("eig.deflate");
+    HIPCHK(launch_deflate(w, st));
+  }
   HIPCHK(mark(2));
-  if (residues && w.k == 2) HIPCHK(launch_alpha_locate(w, st));
-  HIPCHK(launch_polecount(w, st));
-  HIPCHK(launch_locate(w, st));
+  {
+    TraceRange r("eig.locate");
+    if (residues && w.k == 2) HIPCHK(launch_alpha_locate(w, st));
+    HIPCHK(launch_polecount(w, st));
+    HIPCHK(launch_locate(w, st));
+  }
   HIPCHK(mark(3));
-  HIPCHK(launch_rootsolve(w, st));
+  {
+    TraceRange r("eig.roots");
+    HIPCHK(launch_rootsolve(w, st));
+  }
   HIPCHK(mark(4));
-  HIPCHK(launch_finalize(w, st));
+  {
+    TraceRange r("eig.merge");
+    HIPCHK(launch_finalize(w, st));
+  }
   if (values_only) {
-    if (checks) HIPCHK(launch_debug_checks(w, false, false, 0.0, st));
+    if (checks) {
+      TraceRange r("eig.checks");
+      HIPCHK(launch_debug_checks(w, false, false, 0.0, st));
+    }
     HIPCHK(mark(5));
     HIPCHK(mark(6));
     return EIG_OK;
   }
   const bool ff = farfield && ff_eligible(n, w.k);
   const FarField f = ff ? ff_layout(s->ff_block, n, w.k) : FarField{};
-  if (ff) {
-    HIPCHK(launch_ff_plan(w, f, st));
-    HIPCHK(launch_wbuild_ff(w, f, st));
-  } else {
-    HIPCHK(launch_wbuild(w, st));
+  {
+    TraceRange r("eig.w");
+    if (ff) {
+      HIPCHK(launch_ff_plan(w, f, st));
+      HIPCHK(launch_wbuild_ff(w, f, st));
+    } else {
+      HIPCHK(launch_wbuild(w, st));
+    }
+    HIPCHK(launch_group_reflect(w, st));
   }
-  HIPCHK(launch_group_reflect(w, st));
   HIPCHK(mark(5));
-  if (ff)
-    HIPCHK(launch_qw_farfield(w, f, st));
-  else if (prec == EIG_GEMM_FP64)
-    HIPCHK(launch_dgemm(n, n, n, w.Q_in, n, w.W, n, w.Q_out, n, &w.st->status, st));
-  else
-    HIPCHK(launch_gemm_lp(w, prec, s->lp_block, static_cast<char*>(s->lp_block) + s->lp_bytes / 2,
-                          st));
+  {
+    TraceRange r(ff ? "eig.qw_farfield" : "eig.qw");
+    if (ff)
+      HIPCHK(launch_qw_farfield(w, f, st));
+    else if (prec == EIG_GEMM_FP64)
+      HIPCHK(launch_dgemm(n, n, n, w.Q_in, n, w.W, n, w.Q_out, n, &w.st->status, st));
+    else
+      HIPCHK(launch_gemm_lp(w, prec, s->lp_block,
+                            static_cast<char*>(s->lp_block) + s->lp_bytes / 2, st));
+  }
   HIPCHK(mark(6));
   if (checks) {
+    TraceRange r("eig.checks");
     // W is whole unless the far-field product formed only its near blocks; the
     // reduced products' bound on Q'^T Q' - I is 2 sqrt(n) 4e-6
     const double tol_q = (prec == EIG_GEMM_FP64) ? 1e-9 : 8e-6 * std::sqrt((double)n);
@@ -300,6 +326,7 @@ int eig_state_set(eig_state_t s, int32_t knob, int64_t value) {
 
 int eig_state_upload(eig_state_t s, const double* lambda, const double* Q, int64_t ldq,
                      int32_t ptrs_on_device, void* hip_stream) {
+  TraceRange trace("eig_state_upload");
   if (!s || !lambda || !Q || ldq < s->n || s->lean) return EIG_EINVAL;
   DeviceGuard g(s->device);
   if (!g.ok) return EIG_EDEVICE;
@@ -331,6 +358,7 @@ int eig_state_upload(eig_state_t s, const double* lambda, const double* Q, int64
 
 int eig_update_rankk(eig_state_t s, int64_t k, const double* K, int64_t ldk, const int8_t* sigma,
                      uint32_t mode, void* hip_stream) {
+  TraceRange trace("eig_update_rankk");
   if (!s || !K || !sigma || k < 1 || ldk < s->n || s->lean) return EIG_EINVAL;
   if (k > EIG_KMAX_GENERIC) return EIG_EUNSUPPORTED;
   if (k > s->n || ldk > INT32_MAX) return EIG_EINVAL;
@@ -433,6 +461,7 @@ int eig_update_rankk(eig_state_t s, int64_t k, const double* K, int64_t ldk, con
     auto mark = [&](int e) -> hipError_t {
       return (timed && last && e > 0) ? hipEventRecord(s->ev[e], st) : hipSuccess;
     };
+    TraceRange part_range(parts > 1 ? "eig.part" : "eig.update");
     const int rc = enqueue_part(s, w, prec, farfield, (mode & EIG_LOCATE_RESIDUES) != 0, checks,
                                 vo && last, st, mark);
     if (rc != EIG_OK) return rc;
@@ -456,6 +485,7 @@ int eig_update_interval(eig_state_t s, int64_t k, const double* K, int64_t ldk,
                         const int8_t* sigma, double a, double b, uint32_t mode,
                         double* lambda_out, double* V_out, int64_t ldv, int64_t m_max,
                         int64_t* m_out, void* hip_stream) {
+  TraceRange trace("eig_update_interval");
   if (!s || !K || !sigma || !m_out || k < 1 || ldk < s->n || s->lean) return EIG_EINVAL;
   *m_out = 0;
   if (k > EIG_KMAX) return EIG_EUNSUPPORTED;
@@ -533,6 +563,7 @@ int eig_sturm_chain(eig_state_t s, int64_t k, const double* K, int64_t ldk,
                     const int8_t* sigma, const double* xi, int64_t n_xi, const double* x,
                     int64_t n_x, int64_t* counts, double* c_out, int64_t c_max,
                     eig_chain_info* info, void* hip_stream) {
+  TraceRange trace("eig_sturm_chain");
   if (!s || !K || !sigma || !info || k < 1 || ldk < s->n || s->lean) return EIG_EINVAL;
   if (n_xi < 0 || (n_xi > 0 && !xi) || n_x < 0 || (n_x > 0 && (!x || !counts)) || c_max < 0 ||
       (c_max > 0 && !c_out) || n_x > INT32_MAX)
@@ -614,6 +645,7 @@ int eig_sturm_chain(eig_state_t s, int64_t k, const double* K, int64_t ldk,
 int eig_perturb_first_order(eig_state_t s, int64_t k, const double* K, int64_t ldk,
                             const int8_t* sigma, uint32_t mode, double* lambda_out,
                             double* V_out, int64_t ldv, void* hip_stream) {
+  TraceRange trace("eig_perturb_first_order");
   if (!s || !K || !sigma || !lambda_out || !V_out || k < 1 || ldk < s->n || ldv < s->n ||
       s->lean)
     return EIG_EINVAL;
@@ -651,6 +683,7 @@ int eig_perturb_first_order(eig_state_t s, int64_t k, const double* K, int64_t l
 
 int eig_query(eig_state_t s, double* lambda_out, double* Q_out, int64_t ldq,
               int32_t ptrs_on_device, eig_info* info, void* hip_stream) {
+  TraceRange trace("eig_query");
   if (!s) return EIG_EINVAL;
   if (Q_out && ldq < s->n) return EIG_EINVAL;
   DeviceGuard g(s->device);

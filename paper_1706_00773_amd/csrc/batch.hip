@@ -32,6 +32,7 @@
 #include "eigupd.h"
 #include "internal.h"
 #include "state.h"
+#include "trace.h"
 
 using namespace eigupd;
 
@@ -298,6 +299,7 @@ int eig_batch_get(eig_batch_t b, int32_t knob, int64_t* value) {
 
 int eig_update_batch(eig_batch_t b, const eig_batch_item* items, int32_t count, uint32_t mode,
                      void* hip_stream) {
+  TraceRange trace("eig_update_batch");
   if (!b || !items || count < 1 || count > b->max_items) return EIG_EINVAL;
   if (mode & ~(uint32_t)(EIG_VALUES_ONLY | EIG_QW_FARFIELD)) return EIG_EUNSUPPORTED;
   const bool vo = (mode & EIG_VALUES_ONLY) != 0;

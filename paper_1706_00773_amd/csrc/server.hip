@@ -48,6 +48,7 @@
 #include "eigupd.h"
 #include "internal.h"
 #include "state.h"
+#include "trace.h"
 
 using namespace eigupd;
 
@@ -290,6 +291,7 @@ void fail_request(eig_server_s* s, Request* r, int rc) {
 // EIG_EDEPENDENCY.  Returns the number of requests launched or completed so
 // (or -1 on a launch failure).
 int launch(eig_server_s* s, Slot& sl) {
+  TraceRange trace("eig_server.launch");
   std::vector<Request*> pick;
   std::vector<char> blocked(s->mats.size(), 0);  // head request waits for memory
   size_t kdoubles = 0;
