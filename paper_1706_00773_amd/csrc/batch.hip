@@ -415,7 +415,7 @@ int eig_update_batch(eig_batch_t b, const eig_batch_item* items, int32_t count, 
     const int local = pos - p.off[k];
     const bool ff = p.ff[pos] != 0;  // W and Q' by its own far-field launches
     const int nb[NKIND] = {qtk_blocks(n, k), root_blocks(n), ff ? 0 : wbuild_blocks(n),
-                           ff ? 0 : reflect_blocks(n), solve_blocks(n)};
+                           ff ? 0 : reflect_blocks(n), solve_blocks(n, k)};
     for (int kind = 0; kind < NKIND; ++kind) {
       int* pre = hp + p.poff[k][kind];
       pre[local] = run[k][kind];

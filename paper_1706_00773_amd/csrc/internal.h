@@ -276,7 +276,7 @@ hipError_t launch_dgemm_desc(bool acc, int bt, const GemmDescG* d, const int* pr
 // Group.prefix built from the per-instance counts below).
 int qtk_blocks(int n, int k);
 int root_blocks(int n);   // polecount / rootvec blocks of an instance
-int solve_blocks(int n);  // rootsolve blocks of an instance
+int solve_blocks(int n, int k);  // rootsolve blocks of an instance
 int wbuild_blocks(int n);
 int reflect_blocks(int n);
 int gemm_tiles(int n, int bt);

@@ -32,6 +32,8 @@
 // Partial sums meet in LDS, and wave 0 does the k-by-k work (Jacobi
 // eigen-decomposition: inertia, Newton step, null vector) and writes the next
 // points.
+#include <atomic>
+
 #include "common.h"
 #include "smallmat.h"
 
@@ -64,7 +66,7 @@ __device__ __forceinline__ void wave_sync() {
 // SPLIT) takes poles jb + part, jb + part + SPLIT, ...  Tiles of TP poles go
 // global -> registers (one tile ahead) -> LDS, and every lane of a part reads the
 // same pole.
-template <int K, int TP, int SPLIT, typename F>
+template <int K, int TP, int SPLIT, int UNR = 2, typename F>
 __device__ __forceinline__ void sweep_poles(const double* __restrict__ rd,
                                             const double* __restrict__ ru, int jb, int je,
                                             double tau, double d_o, PoleTile<K, TP>& tile, F&& f) {
@@ -93,7 +95,7 @@ __device__ __forceinline__ void sweep_poles(const double* __restrict__ rd,
     wave_sync();
     if (base + TP < je) load(base + TP);
     const int cnt = min(TP, je - base);
-#pragma unroll 2
+#pragma unroll UNR
     for (int q = part; q < cnt; q += SPLIT) {
       double u[K];
 #pragma unroll
@@ -113,19 +115,15 @@ __device__ __forceinline__ void combine_parts(double (&a)[N]) {
     for (int e = 0; e < N; ++e) a[e] += __shfl_xor(a[e], off, 64);
 }
 
-// S = sum_j u_j u_j^T r_j (without -Sigma) and G = sum_j (u_j r_j)(u_j r_j)^T over this
-// wave's poles, combined across the parts of the wave.
+// S = sum_j u_j u_j^T r_j (without -Sigma) over this wave's poles, combined across
+// the parts of the wave.
 template <int K, int TP, int SPLIT>
 __device__ __forceinline__ void sweep(const double* __restrict__ rd, const double* __restrict__ ru,
                                       int jb, int je, double tau, double d_o,
-                                      double (&S)[Sym<K>::NS], double (&G)[Sym<K>::NS],
-                                      PoleTile<K, TP>& tile) {
+                                      double (&S)[Sym<K>::NS], PoleTile<K, TP>& tile) {
   constexpr int NS = Sym<K>::NS;
 #pragma unroll
-  for (int e = 0; e < NS; ++e) {
-    S[e] = 0.0;
-    G[e] = 0.0;
-  }
+  for (int e = 0; e < NS; ++e) S[e] = 0.0;
   sweep_poles<K, TP, SPLIT>(rd, ru, jb, je, tau, d_o, tile, [&](double r, const double (&u)[K]) {
     double v[K];
 #pragma unroll
@@ -133,30 +131,37 @@ __device__ __forceinline__ void sweep(const double* __restrict__ rd, const doubl
 #pragma unroll
     for (int a = 0; a < K; ++a)
 #pragma unroll
-      for (int b = a; b < K; ++b) {
-        S[Sym<K>::at(a, b)] = fma(u[a], v[b], S[Sym<K>::at(a, b)]);
-        G[Sym<K>::at(a, b)] = fma(v[a], v[b], G[Sym<K>::at(a, b)]);
-      }
+      for (int b = a; b < K; ++b) S[Sym<K>::at(a, b)] = fma(u[a], v[b], S[Sym<K>::at(a, b)]);
   });
   combine_parts<SPLIT>(S);
-  combine_parts<SPLIT>(G);
 }
 
 // Pole value written into the unused tail of a tile: with u = 0 it contributes
 // nothing, and tau - (PAD_D - d_o) is never 0.
 constexpr double PAD_D = 1e300;
 
-// As sweep(), and also e = sum_j sum_a |u_ja v_ja| = sum_j ||u_j||^2 |r_j|, the size
-// of the terms summed into the diagonal of S, which bounds its rounding error.
+// The root solver's tile: the poles and, per pole, ||u_j||^2.
+template <int K, int TP>
+struct RootTile {
+  double d[TP];
+  double nrm[TP];
+  double u[TP][K];
+};
+
+// As sweep(), and also e = sum_j ||u_j||^2 |r_j| (= sum_j sum_a |u_ja v_ja|), the
+// size of the terms summed into the diagonal of S, which bounds its rounding
+// error; ||u_j||^2 is formed once per tile, not once per root.
 // For the root solver only: x is strictly between two poles, so 1/(x - d_j) needs
 // no guard, and the pole loop is the same for every lane (the tile tail is padded
 // with zero-weight poles), which lets the compiler pipeline the LDS reads.
+// r_j takes one Newton step from the hardware estimate (relative error ~1e-15,
+// well below the rounding of the sums it enters).
 template <int K, int TP, int SPLIT, int UNR = 4>
 __device__ __forceinline__ void sweep_err(const double* __restrict__ rd,
                                           const double* __restrict__ ru, int jb, int je,
                                           double tau, double d_o, double (&S)[Sym<K>::NS],
                                           double (&G)[Sym<K>::NS], double& e,
-                                          PoleTile<K, TP>& tile) {
+                                          RootTile<K, TP>& tile) {
   static_assert(TP % SPLIT == 0, "a padded tile holds whole rounds");
   constexpr int NS = Sym<K>::NS;
   constexpr int PER = TP / 64;
@@ -183,9 +188,14 @@ __device__ __forceinline__ void sweep_err(const double* __restrict__ rd,
   for (int base = jb; base < je; base += TP) {
 #pragma unroll
     for (int p = 0; p < PER; ++p) {
-      tile.d[p * 64 + lane] = pd[p];
+      double nn = 0.0;
 #pragma unroll
-      for (int c = 0; c < K; ++c) tile.u[p * 64 + lane][c] = pu[p][c];
+      for (int c = 0; c < K; ++c) {
+        tile.u[p * 64 + lane][c] = pu[p][c];
+        nn = fma(pu[p][c], pu[p][c], nn);
+      }
+      tile.d[p * 64 + lane] = pd[p];
+      tile.nrm[p * 64 + lane] = nn;
     }
     wave_sync();
     if (base + TP < je) load(base + TP);
@@ -196,19 +206,14 @@ __device__ __forceinline__ void sweep_err(const double* __restrict__ rd,
       double u[K], v[K];
 #pragma unroll
       for (int c = 0; c < K; ++c) u[c] = tile.u[q][c];
-      double r = __builtin_amdgcn_rcp(tau - (tile.d[q] - d_o));
-      {
-        const double y = tau - (tile.d[q] - d_o);
-        double t = fma(-y, r, 1.0);
-        r = fma(r, t, r);
-        t = fma(-y, r, 1.0);
-        r = fma(r, t, r);
-      }
+      const double y = tau - (tile.d[q] - d_o);
+      double r = __builtin_amdgcn_rcp(y);
+      r = fma(r, fma(-y, r, 1.0), r);
+      acc_e[0] = fma(tile.nrm[q], fabs(r), acc_e[0]);
 #pragma unroll
       for (int c = 0; c < K; ++c) v[c] = u[c] * r;
 #pragma unroll
       for (int a = 0; a < K; ++a) {
-        acc_e[0] = fma(fabs(u[a]), fabs(v[a]), acc_e[0]);
 #pragma unroll
         for (int b = a; b < K; ++b) {
           S[Sym<K>::at(a, b)] = fma(u[a], v[b], S[Sym<K>::at(a, b)]);
@@ -244,9 +249,9 @@ __device__ __forceinline__ void polecount_body(const Work& w, int bid) {
   const double d_s = w.rd[st];
   const int chunk = (n_d + WV - 1) / WV;
   const int jb = min(n_d, wv * chunk), je = min(n_d, jb + chunk);
-  double T[NS], G[NS];
+  double T[NS];
   // tau = 0 at origin d_s: x - d_j = d_s - d_j; rows of segment s give 0 and are skipped
-  sweep<K, TP, Cfg<K>::SPLIT>(w.rd, w.ru, jb, je, 0.0, d_s, T, G, s_tile[wv]);
+  sweep<K, TP, Cfg<K>::SPLIT>(w.rd, w.ru, jb, je, 0.0, d_s, T, s_tile[wv]);
   if (lane < RPB) {
 #pragma unroll
     for (int e = 0; e < NS; ++e) s_part[wv][e][slot] = T[e];
@@ -354,6 +359,10 @@ constexpr double NOISE_C = 64.0;
 // without another evaluation.
 constexpr double QUAD_R = 1e-3;
 
+#ifndef ROWS_MIN_K
+#define ROWS_MIN_K 8
+#endif
+
 // Launch shape of the root solver: RPB root slots per block, each slot's pole
 // sums split over WV waves x SPLIT parts of a wave.  A slot whose root has
 // converged takes the next unsolved root of the update (a counter in DevInfo),
@@ -388,8 +397,10 @@ template <int K>
 __device__ __forceinline__ void rootsolve_body(const Work& w) {
   constexpr int NS = Sym<K>::NS, WV = RsCfg<K>::WV, RPB = RsCfg<K>::RPB, TP = RsCfg<K>::TP;
   constexpr int SPLIT = RsCfg<K>::SPLIT;
+  constexpr int KV = (K >= ROWS_MIN_K) ? K : 1;  // eigenvectors of the lane-group solve
   __shared__ double s_part[WV][2 * NS + 1][RPB];
-  __shared__ PoleTile<K, TP> s_tile[WV];
+  __shared__ RootTile<K, TP> s_tile[WV];
+  __shared__ double s_V[RPB][KV][KV];
   __shared__ SlotState s_st[RPB];
   __shared__ double s_tau[RPB], s_do[RPB];
   __shared__ int s_any;
@@ -485,67 +496,111 @@ __device__ __forceinline__ void rootsolve_body(const Work& w) {
     }
     __syncthreads();
     if (wv == 0) {
-      bool live = false;
-      if (owner && s_st[slot].phase != PH_DONE) {
-        SlotState z = s_st[slot];
-        // ranks >= 5 keep the totals of G in LDS (wave 0's row of s_part, which no
-        // other wave touches before the next sweep) so that they are not live
-        // through the k x k eigensolve
-        constexpr bool G_IN_LDS = (K >= 5);
-        constexpr int NG = G_IN_LDS ? 1 : NS;
-        double S[NS], G[NG];
-        double err = (double)K;  // the -Sigma diagonal
-#pragma unroll
-        for (int e = 0; e < NS; ++e) S[e] = 0.0;
-#pragma unroll
-        for (int e = 0; e < NG; ++e) G[e] = 0.0;
+      // S(x) = V diag(theta) V^T: the inertia of S, its smallest |theta|, and
+      // tr(S^{-1} S') = -sum_m v_m^T G v_m / theta_m.  Ranks >= 5 solve the k x k
+      // problem on a group of 8 lanes per slot (lane l: row l), lower ranks on
+      // one lane per slot.
+      constexpr bool ROWS = (K >= ROWS_MIN_K);
+      const int es = ROWS ? (lane >> 3) : slot;
+      const bool eowner = ROWS ? ((lane & 7) == 0) : (lane < RPB);
+      const bool elive = s_st[es].phase != PH_DONE;
+      int neg = 0;
+      double phi = 0.0, thmin = INFINITY;
+      double err = (double)K;  // the -Sigma diagonal
 #pragma unroll 1
-        for (int q = 0; q < WV; ++q) {
+      for (int q = 0; q < WV; ++q) err += s_part[q][2 * NS][es];
+      if constexpr (ROWS) {
+        const int l = lane & 7;
+        double a[K], v[K];
 #pragma unroll
-          for (int e = 0; e < NS; ++e) S[e] += s_part[q][e][slot];
-          if constexpr (!G_IN_LDS) {
-#pragma unroll
-            for (int e = 0; e < NS; ++e) G[e] += s_part[q][NS + e][slot];
+        for (int c = 0; c < K; ++c) {
+          double x = 0.0;
+          if (l < K) {
+            for (int q = 0; q < WV; ++q) x += s_part[q][Sym<K>::at(l, c)][es];
+            if (c == l) x -= ((w.sig_pos_mask >> c) & 1) ? 1.0 : -1.0;
           }
-          err += s_part[q][2 * NS][slot];
+          a[c] = x;
         }
-        if constexpr (G_IN_LDS) {
-#pragma unroll 1
-          for (int e = 0; e < NS; ++e) {
-            double g = 0.0;
-            for (int q = 0; q < WV; ++q) g += s_part[q][NS + e][slot];
-            s_part[0][NS + e][slot] = g;
-          }
+        // the totals of G into wave 0's row of s_part (entries striped over the group)
+        for (int e = l; e < NS; e += 8) {
+          double g = 0.0;
+          for (int q = 0; q < WV; ++q) g += s_part[q][NS + e][es];
+          s_part[0][NS + e][es] = g;
         }
-        auto Gat = [&](int e) -> double {
-          if constexpr (G_IN_LDS)
-            return s_part[0][NS + e][slot];
-          else
-            return G[e];
-        };
+        jacobi_eig_rows<K, true>(a, v, elive);
+        const double th = (l < K) ? row_at<K>(a, l) : 0.0;
+        if (l < K) {
 #pragma unroll
-        for (int c = 0; c < K; ++c)
-          S[Sym<K>::at(c, c)] -= ((w.sig_pos_mask >> c) & 1) ? 1.0 : -1.0;
-        // S(x) = V diag(theta) V^T: inertia, and tr(S^{-1} S') = -sum_m v_m^T G v_m / theta_m
-        double V[K][K];
-        jacobi_eig<K, true>(S, V);
-        int neg = 0;
-        double phi = 0.0, thmin = INFINITY;
+          for (int c = 0; c < K; ++c) s_V[es][l][c] = v[c];
+        }
+        wave_sync();
+        // lane m < K: the eigenvector v_m of theta_m is column m of V
+        double term = 0.0;
+        if (l < K) {
+          double col[K];
 #pragma unroll
-        for (int m = 0; m < K; ++m) {
-          const double th = S[Sym<K>::at(m, m)];
-          neg += (th < 0.0) ? 1 : 0;
-          thmin = fmin(thmin, fabs(th));
+          for (int r = 0; r < K; ++r) col[r] = s_V[es][r][l];
           double vgv = 0.0;
 #pragma unroll
           for (int p2 = 0; p2 < K; ++p2) {
             double gv = 0.0;
 #pragma unroll
-            for (int q2 = 0; q2 < K; ++q2) gv += Gat(Sym<K>::at(p2, q2)) * V[q2][m];
-            vgv += V[p2][m] * gv;
+            for (int q2 = 0; q2 < K; ++q2) gv += s_part[0][NS + Sym<K>::at(p2, q2)][es] * col[q2];
+            vgv += col[p2] * gv;
           }
-          phi -= vgv / th;
+          term = -vgv / th;
         }
+        phi = group8_sum(term);
+        neg = group8_sum_int((l < K && th < 0.0) ? 1 : 0);
+        thmin = group8_min((l < K) ? fabs(th) : INFINITY);
+      } else if (eowner && elive) {
+        double S[NS], G[NS];
+#pragma unroll
+        for (int e = 0; e < NS; ++e) S[e] = G[e] = 0.0;
+#pragma unroll 1
+        for (int q = 0; q < WV; ++q) {
+#pragma unroll
+          for (int e = 0; e < NS; ++e) {
+            S[e] += s_part[q][e][es];
+            G[e] += s_part[q][NS + e][es];
+          }
+        }
+#pragma unroll
+        for (int c = 0; c < K; ++c)
+          S[Sym<K>::at(c, c)] -= ((w.sig_pos_mask >> c) & 1) ? 1.0 : -1.0;
+        if constexpr (K >= 5) {
+          // G rotated along with S: on return G holds V^T G V
+          jacobi_eig_congruent<K>(S, G);
+#pragma unroll
+          for (int m = 0; m < K; ++m) {
+            const double th = S[Sym<K>::at(m, m)];
+            neg += (th < 0.0) ? 1 : 0;
+            thmin = fmin(thmin, fabs(th));
+            phi -= G[Sym<K>::at(m, m)] / th;
+          }
+        } else {
+          double V[K][K];
+          jacobi_eig<K, true>(S, V);
+#pragma unroll
+          for (int m = 0; m < K; ++m) {
+            const double th = S[Sym<K>::at(m, m)];
+            neg += (th < 0.0) ? 1 : 0;
+            thmin = fmin(thmin, fabs(th));
+            double vgv = 0.0;
+#pragma unroll
+            for (int p2 = 0; p2 < K; ++p2) {
+              double gv = 0.0;
+#pragma unroll
+              for (int q2 = 0; q2 < K; ++q2) gv += G[Sym<K>::at(p2, q2)] * V[q2][m];
+              vgv += V[p2][m] * gv;
+            }
+            phi -= vgv / th;
+          }
+        }
+      }
+      bool live = false;
+      if (eowner && elive) {
+        SlotState z = s_st[es];
         ++z.evals;
         const int tgt = z.i + 1;
         const int cnt = z.rows_below + neg - w.info->p;
@@ -630,9 +685,9 @@ __device__ __forceinline__ void rootsolve_body(const Work& w) {
           z.it_sum += z.evals;
           start(z);
         }
-        s_st[slot] = z;
-        s_tau[slot] = z.tau;
-        s_do[slot] = z.d_o;
+        s_st[es] = z;
+        s_tau[es] = z.tau;
+        s_do[es] = z.d_o;
         live = z.phase != PH_DONE;
       }
       const unsigned long long any = __ballot(live);
@@ -667,10 +722,156 @@ __device__ __forceinline__ void rootsolve_body(const Work& w) {
 // ---------------------------------------------------------------------------
 constexpr double CLUSTER_TOL = 1e-8;
 
+// Ranks from RV_ROWS_MIN_K up solve rootvec's k x k problems on groups of 8 lanes
+// (one row of the matrix per lane), as the root solver does from ROWS_MIN_K up.
+#ifndef RV_ROWS_MIN_K
+#define RV_ROWS_MIN_K 6
+#endif
+
+// The end of rootvec on groups of 8 lanes: every lane of the block calls it once
+// the Gram sums of the candidates are in s_part.  Slots whose root is simple
+// normalise their first candidate (one lane per slot); the slots of a cluster
+// orthonormalise the candidates in the Gram inner product (one lane per slot,
+// the coefficient vectors X in LDS) and then take the Ritz vector of their rank
+// from the eigenpairs of the k x k Rayleigh quotient H, solved on the lane groups.
+// X and H of slot s overwrite the partial sums of slot s in s_part once they
+// have been added up.
+template <int K, int WV, int RPB>
+__device__ __forceinline__ void rootvec_finish_rows(const Work& w, int i0, int r_hi,
+                                                    double (&s_part)[WV][2 * Sym<K>::NS][RPB],
+                                                    double (&s_C)[K][K][RPB],
+                                                    double (&s_th)[K][RPB],
+                                                    const double (&s_tau)[RPB],
+                                                    const int (&s_mc)[RPB],
+                                                    const int (&s_pos)[RPB], int cluster) {
+  constexpr int NS = Sym<K>::NS;
+  static_assert(K * K <= 2 * NS && WV >= 2, "X and H fit in a slot's partial sums");
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int slot = lane % RPB;
+  const bool owner = (wv == 0) && (lane < RPB);
+  if (owner && i0 + slot < r_hi) {
+    const int i = i0 + slot;
+    double gram[NS];
+#pragma unroll
+    for (int e = 0; e < NS; ++e) {
+      double as = 0.0;
+      for (int q = 0; q < WV; ++q) as += s_part[q][e][slot];
+      gram[e] = as;
+    }
+    const int m_c = min(s_mc[slot], K);
+    if (m_c == 1) {
+      const double inv = (gram[0] > 0.0) ? 1.0 / sqrt(gram[0]) : 0.0;
+#pragma unroll
+      for (int c = 0; c < K; ++c) w.root_c[(size_t)i * K + c] = s_C[0][c][slot] * inv;
+      w.root_tv[i] = s_tau[slot];
+    } else {
+      // Gram-Schmidt of the m_c candidates in the Gram inner product, on
+      // coefficient vectors (candidate a is e_a); rows r >= m_c stay zero
+      auto X = [&](int r, int a) -> double& { return s_part[0][r * K + a][slot]; };
+      auto quadx = [&](const double (&B)[NS], int r1, int r2) {
+        double acc = 0.0;
+#pragma unroll
+        for (int a = 0; a < K; ++a) {
+          double t = 0.0;
+#pragma unroll
+          for (int b = 0; b < K; ++b) t += B[Sym<K>::at(a, b)] * X(r2, b);
+          acc += X(r1, a) * t;
+        }
+        return acc;
+      };
+#pragma unroll 1
+      for (int r = 0; r < K; ++r)
+#pragma unroll
+        for (int a = 0; a < K; ++a) X(r, a) = (r == a && r < m_c) ? 1.0 : 0.0;
+#pragma unroll 1
+      for (int r = 0; r < m_c; ++r) {
+#pragma unroll 1
+        for (int l2 = 0; l2 < r; ++l2) {
+          const double g = quadx(gram, l2, r);
+#pragma unroll
+          for (int a = 0; a < K; ++a) X(r, a) -= g * X(l2, a);
+        }
+        const double nn = sqrt(fmax(quadx(gram, r, r), 0.0));
+        const double inv = (nn > 0.0) ? 1.0 / nn : 0.0;
+#pragma unroll
+        for (int a = 0; a < K; ++a) X(r, a) *= inv;
+      }
+      // Rayleigh-Ritz: in candidate coordinates S acts as diag(theta), so
+      // C^T (S Sigma S + S) C = Theta (Cc^T Sigma Cc) Theta + Theta
+      double Hc[NS];
+      double hscale = 0.0;
+#pragma unroll
+      for (int a = 0; a < K; ++a) {
+        hscale = fmax(hscale, fabs(s_th[a][slot]));
+#pragma unroll
+        for (int b = a; b < K; ++b) {
+          double m = 0.0;
+#pragma unroll
+          for (int c = 0; c < K; ++c)
+            m += s_C[a][c][slot] * (((w.sig_pos_mask >> c) & 1) ? 1.0 : -1.0) * s_C[b][c][slot];
+          Hc[Sym<K>::at(a, b)] =
+              s_th[a][slot] * m * s_th[b][slot] + ((a == b) ? s_th[a][slot] : 0.0);
+        }
+      }
+#pragma unroll 1
+      for (int r = 0; r < K; ++r)
+#pragma unroll 1
+        for (int q = r; q < K; ++q) {
+          double acc = (r == q) ? 4.0 * hscale + 1.0 : 0.0;
+          if (r < m_c && q < m_c) acc = quadx(Hc, r, q);
+          s_part[1][Sym<K>::at(r, q)][slot] = acc;
+        }
+    }
+  }
+  if (!cluster) return;
+  __syncthreads();
+  // the eigenpairs of H on the lane groups, and the Ritz vector of rank pos
+  const int l = lane & 7;
+#pragma unroll 1
+  for (int pass = 0; pass < RPB / (8 * WV); ++pass) {
+    const int gs = (pass * WV + wv) * 8 + (lane >> 3);
+    const int m_c = min(s_mc[gs], K);
+    const bool live = (i0 + gs < r_hi) && m_c > 1;
+    if (__ballot(live) == 0ull) continue;
+    double a[K], v[K];
+#pragma unroll
+    for (int c = 0; c < K; ++c) a[c] = (live && l < K) ? s_part[1][Sym<K>::at(l, c)][gs] : 0.0;
+    jacobi_eig_rows<K, true>(a, v, live);
+    const double hv = row_at<K>(a, l);
+    const int pos = min(max(s_pos[gs], 0), m_c - 1);
+    double y = 0.0;  // Y(l, m*), m* the eigenvector of ascending rank pos
+#pragma unroll
+    for (int m = 0; m < K; ++m) {
+      const double hm = __shfl(hv, (lane & ~7) + m, 64);
+      int rk = 0;
+#pragma unroll
+      for (int m2 = 0; m2 < K; ++m2) {
+        const double h2 = __shfl(hv, (lane & ~7) + m2, 64);
+        rk += (h2 < hm || (h2 == hm && m2 < m)) ? 1 : 0;
+      }
+      if (rk == pos) y = v[m];
+    }
+    // z = sum_r Y(r, m*) X(r, :) over the group, then this lane's entry of C z
+    double out = 0.0;
+#pragma unroll
+    for (int a2 = 0; a2 < K; ++a2) {
+      const double za = group8_sum((live && l < K) ? y * s_part[0][l * K + a2][gs] : 0.0);
+      out = fma(za, (l < K) ? s_C[a2][l][gs] : 0.0, out);
+    }
+    if (live && l < K) {
+      const int i = i0 + gs;
+      w.root_c[(size_t)i * K + l] = out;
+      if (l == 0) w.root_tv[i] = s_tau[gs];
+    }
+  }
+}
+
 template <int K>
 __device__ __forceinline__ void rootvec_body(const Work& w, int bid) {
   constexpr int NS = Sym<K>::NS, WV = Cfg<K>::WV, RPB = Cfg<K>::RPB, TP = Cfg<K>::TP;
   constexpr int SPLIT = Cfg<K>::SPLIT;
+  constexpr bool ROWS = (K >= RV_ROWS_MIN_K);
+  static_assert(!ROWS || (RPB % (8 * WV)) == 0, "whole passes of lane groups");
   __shared__ double s_part[WV][2 * NS][RPB];
   __shared__ PoleTile<K, TP> s_tile[WV];
   __shared__ double s_C[K][K][RPB];
@@ -715,14 +916,56 @@ __device__ __forceinline__ void rootvec_body(const Work& w, int bid) {
   }
   __syncthreads();
   const double tau = s_tau[slot], d_o = s_do[slot];
-  double S[NS], G[NS];
-  sweep<K, TP, SPLIT>(w.rd, w.ru, jb, je, tau, d_o, S, G, s_tile[wv]);
-  if (lane < RPB) {
+  {
+    double S[NS];
+    sweep<K, TP, SPLIT>(w.rd, w.ru, jb, je, tau, d_o, S, s_tile[wv]);
+    if (lane < RPB) {
 #pragma unroll
-    for (int e = 0; e < NS; ++e) s_part[wv][e][slot] = S[e];
+      for (int e = 0; e < NS; ++e) s_part[wv][e][slot] = S[e];
+    }
   }
   __syncthreads();
-  if (owner) {
+  if constexpr (ROWS) {
+    // the eigenpairs of S for every slot, on groups of 8 lanes (lane l: row l);
+    // each wave takes 8 slots per pass
+    const int l = lane & 7;
+#pragma unroll 1
+    for (int pass = 0; pass < RPB / (8 * WV); ++pass) {
+      const int gs = (pass * WV + wv) * 8 + (lane >> 3);
+      double a[K], v[K];
+#pragma unroll
+      for (int c = 0; c < K; ++c) {
+        double x = 0.0;
+        if (l < K) {
+          for (int q = 0; q < WV; ++q) x += s_part[q][Sym<K>::at(l, c)][gs];
+          if (c == l) x -= ((w.sig_pos_mask >> c) & 1) ? 1.0 : -1.0;
+        }
+        a[c] = x;
+      }
+      jacobi_eig_rows<K, true>(a, v, i0 + gs < r_hi);
+      // candidates: eigenvectors of S ordered by |theta| ascending (column m of V
+      // is spread over the group: this lane holds its entry l)
+      const double th = row_at<K>(a, l);
+      double ths[K];
+#pragma unroll
+      for (int m = 0; m < K; ++m) ths[m] = __shfl(th, (lane & ~7) + m, 64);
+      if (l < K) {
+#pragma unroll
+        for (int m = 0; m < K; ++m) {
+          const double am = fabs(ths[m]);
+          int rk = 0;
+#pragma unroll
+          for (int m2 = 0; m2 < K; ++m2) {
+            const double a2 = fabs(ths[m2]);
+            rk += (a2 < am || (a2 == am && m2 < m)) ? 1 : 0;
+          }
+          s_C[rk][l][gs] = v[m];
+          if (l == m) s_th[rk][gs] = ths[m];
+        }
+      }
+    }
+  } else if (owner) {
+    double S[NS];
 #pragma unroll
     for (int e = 0; e < NS; ++e) {
       double as = 0.0;
@@ -766,6 +1009,30 @@ __device__ __forceinline__ void rootvec_body(const Work& w, int bid) {
                                 z *= r;
                                 gram[0] = fma(z, z, gram[0]);
                               });
+  } else if constexpr (ROWS) {
+    // the candidates stay in LDS (k^2 coefficients per lane would not fit in
+    // registers next to the Gram sums)
+    sweep_poles<K, TP, SPLIT, 1>(w.rd, w.ru, jb, je, tau, d_o, s_tile[wv],
+                              [&](double r, const double (&u)[K]) {
+                                // an opaque slot index: the candidates are read
+                                // per pole, not hoisted out of the loop
+                                int sl = slot;
+                                asm volatile("" : "+v"(sl));
+                                double z[K];
+#pragma unroll
+                                for (int a = 0; a < K; ++a) {
+                                  double t = 0.0;
+#pragma unroll
+                                  for (int c = 0; c < K; ++c) t = fma(u[c], s_C[a][c][sl], t);
+                                  z[a] = t * r;
+                                }
+#pragma unroll
+                                for (int a = 0; a < K; ++a)
+#pragma unroll
+                                  for (int b = a; b < K; ++b)
+                                    gram[Sym<K>::at(a, b)] =
+                                        fma(z[a], z[b], gram[Sym<K>::at(a, b)]);
+                              });
   } else {
     double Cm[K][K];
 #pragma unroll
@@ -797,6 +1064,11 @@ __device__ __forceinline__ void rootvec_body(const Work& w, int bid) {
     for (int e = 0; e < NS; ++e) s_part[wv][e][slot] = gram[e];
   }
   __syncthreads();
+  if constexpr (ROWS) {
+    rootvec_finish_rows<K, WV, RPB>(w, i0, r_hi, s_part, s_C, s_th, s_tau, s_mc, s_pos,
+                                    s_cluster);
+    return;
+  }
   if (!owner || i0 + slot >= r_hi) return;
 #pragma unroll
   for (int e = 0; e < NS; ++e) {
@@ -1219,9 +1491,48 @@ __global__ __launch_bounds__(64 * Cfg<K>::WV) void rootvec_group(Group g) {
 }
 
 int root_blocks(int n) { return (n + 31) / 32; }
-// Two roots per slot on average: enough blocks for two per CU at n = 8192, few
-// enough that a slot's refills balance the roots' differing iteration counts.
-int solve_blocks(int n) { return (n + 2 * 8 - 1) / (2 * 8); }
+// Root-solver blocks the device holds at once (CUs x resident blocks per CU),
+// looked up once per rank.
+template <int K>
+static int resident_solve_blocks_k() {
+  static std::atomic<int> cached{0};
+  int v = cached.load(std::memory_order_relaxed);
+  if (v > 0) return v;
+  int dev = 0, cus = 0, per = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(
+          &per, reinterpret_cast<const void*>(&rootsolve_kernel<K>), 64 * RsCfg<K>::WV, 0) !=
+          hipSuccess) {
+    (void)hipGetLastError();
+    return 0;
+  }
+  v = max(cus * per, 1);
+  cached.store(v, std::memory_order_relaxed);
+  return v;
+}
+static int resident_solve_blocks(int k) {
+  switch (k) {
+    case 1: return resident_solve_blocks_k<1>();
+    case 2: return resident_solve_blocks_k<2>();
+    case 3: return resident_solve_blocks_k<3>();
+    case 4: return resident_solve_blocks_k<4>();
+    case 5: return resident_solve_blocks_k<5>();
+    case 6: return resident_solve_blocks_k<6>();
+    case 7: return resident_solve_blocks_k<7>();
+    default: return resident_solve_blocks_k<8>();
+  }
+}
+
+// Two roots per slot on average (a slot's refills balance the roots' differing
+// iteration counts), but as many blocks as the device holds at once where that
+// is more -- ranks whose solver fits several blocks per CU would otherwise
+// leave CUs idle -- up to one root per slot.  The grid does not change the
+// result of any root: every slot sums the same pole partition in the same order.
+int solve_blocks(int n, int k) {
+  const int two = (n + 2 * 8 - 1) / (2 * 8), one = (n + 8 - 1) / 8;
+  return max(two, min(one, resident_solve_blocks(k)));
+}
 
 template <int K>
 static hipError_t polecount_group_launch(const Group& g, int blocks, hipStream_t s) {
@@ -1235,16 +1546,22 @@ static hipError_t rootsolve_group_launch(const Group& gs, int solve_blocks, cons
                                          int vec_blocks, int persistent_grid, int* queue,
                                          hipStream_t s) {
   hipError_t e;
-  if (persistent_grid > 0) {
-    hipLaunchKernelGGL(zero_ints_kernel, dim3(1), dim3(64), 0, s, queue, 1);
-    e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((rootsolve_persist<K>), dim3(min(persistent_grid, solve_blocks)),
-                       dim3(64 * RsCfg<K>::WV), 0, s, gs, solve_blocks, queue);
-  } else {
+  bool persistent = false;
+  // ranks >= 7: the persistent loop around the solver does not fit its
+  // registers; the grouped launch computes the same numbers
+  if constexpr (K <= 6) {
+    if (persistent_grid > 0) {
+      hipLaunchKernelGGL(zero_ints_kernel, dim3(1), dim3(64), 0, s, queue, 1);
+      e = hipGetLastError();
+      if (e != hipSuccess) return e;
+      hipLaunchKernelGGL((rootsolve_persist<K>), dim3(min(persistent_grid, solve_blocks)),
+                         dim3(64 * RsCfg<K>::WV), 0, s, gs, solve_blocks, queue);
+      persistent = true;
+    }
+  }
+  if (!persistent)
     hipLaunchKernelGGL((rootsolve_group<K>), dim3(solve_blocks), dim3(64 * RsCfg<K>::WV), 0, s,
                        gs);
-  }
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL((rootvec_group<K>), dim3(vec_blocks), dim3(64 * Cfg<K>::WV), 0, s, gv);
@@ -1281,7 +1598,7 @@ template <int K>
 static hipError_t rootsolve_launch(const Work& w, int nroots, hipStream_t s) {
   if (nroots <= 0) return hipSuccess;
   static_assert(RsCfg<K>::RPB == 8, "solve_blocks assumes 8 slots per block");
-  hipLaunchKernelGGL((rootsolve_kernel<K>), dim3(solve_blocks(nroots)), dim3(64 * RsCfg<K>::WV),
+  hipLaunchKernelGGL((rootsolve_kernel<K>), dim3(solve_blocks(nroots, K)), dim3(64 * RsCfg<K>::WV),
                      0, s, w);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;

@@ -386,3 +386,36 @@ def test_double_root_away_from_poles():
     assert np.abs(lo - ev).max() <= 1e-14
     assert np.abs(Qo.T @ Qo - np.eye(4)).max() <= 1e-10
     assert np.abs(A @ Qo - Qo * lo).max() <= 1e-10
+
+
+@pytest.mark.parametrize("k,m", [(3, 3), (6, 2), (6, 6), (7, 7), (8, 3), (8, 8)])
+def test_multiple_root_cluster(k, m):
+    """k decoupled rank-1 blocks, each with one pole at or below 0 and one at or
+    above 1, m of them with their root at the same r in (0, 1): an m-fold
+    eigenvalue inside one pole interval (the cluster branch for a group of m
+    roots), next to k - m simple roots in the same interval.  Eigenvalues against
+    LAPACK on the explicit matrix; residual and orthonormality of every column."""
+    print(f"case multiple-root cluster k={k} m={m}", flush=True)
+    r = 0.37
+    lam = np.empty(2 * k)
+    K = np.zeros((2 * k, k))
+    for b in range(k):
+        a, c = -0.1 * b, 1.0 + 0.1 * b
+        rb = r if b < m else 0.05 + 0.9 * (b - m + 1) / (k - m + 1)
+        za2 = 2.0 * (rb - a)  # 1 + za^2 / (a - rb) = -1
+        lam[2 * b], lam[2 * b + 1] = a, c
+        K[2 * b, b] = np.sqrt(za2)
+        K[2 * b + 1, b] = np.sqrt(c - rb)  # f_b(rb) = -1 + zc^2 / (c - rb) = 0
+    order = np.argsort(lam)
+    lam, K = lam[order], K[order]
+    sig = np.ones(k, dtype=np.int8)
+    rng = np.random.default_rng(40 + k + m)
+    Q = wl.orthogonal_from(rng.standard_normal((2 * k, 2 * k)))
+    Kq = np.asfortranarray(np.asarray(Q) @ K)
+    lo, Qo, info, _ = run_update(lam, Q, Kq, sig)
+    A = wl.explicit_matrix(lam, Q, Kq, sig)
+    ev = np.linalg.eigvalsh(A)
+    assert np.sum(np.abs(ev - r) < 1e-12) == m
+    assert np.abs(lo - ev).max() <= 1e-13
+    assert np.abs(Qo.T @ Qo - np.eye(2 * k)).max() <= 1e-10
+    assert np.abs(A @ Qo - Qo * lo).max() <= 1e-10
