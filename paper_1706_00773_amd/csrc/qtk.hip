@@ -2,12 +2,15 @@
 //
 // Q is n-by-n column-major (leading dimension ldq >= n) and K n-by-k with
 // k <= 8, so U is a skinny product bound by streaming Q from HBM once
-// (8 n^2 bytes, 2 n^2 k flops).  A block of 256 threads owns CPB consecutive
-// columns of Q: each thread walks row pairs r = 2 tid, 2 tid + 512, ...
-// (16-byte loads, coalesced along the column; rows tid, tid + 256, ... when n
-// or ldq is odd), keeps K's rows in registers for all CPB columns, and the
-// block reduces CPB*k partial sums at the end.  Non-finite entries of U raise
-// the sticky ST_NONFINITE bit.
+// (8 n^2 bytes, 2 n^2 k flops).  A block of 256 threads owns CPB = 2
+// consecutive columns of Q: each thread takes the row pairs r = 2 tid + 1024 i
+// and r + 512 (16-byte streaming loads, coalesced along the column, all four
+// issued before any is used; rows tid, tid + 256, ... when n or ldq is odd),
+// combines them with K's rows, and the block reduces CPB*k partial sums at the
+// end.  Few columns per block keep the concurrent streams of a CU close
+// together in memory; measured at n = 8192 this runs at the read-only streaming
+// rate of the chip (more columns per block, or one pair per thread, did not).
+// Non-finite entries of U raise the sticky ST_NONFINITE bit.
 #include "common.h"
 
 namespace eigupd {
@@ -27,20 +30,36 @@ __device__ __forceinline__ void qtk_body(const Work& w, int bid) {
   const size_t ldq = (size_t)w.ldq;
   const int ncol = min(CPB, n - j0);
   if (!(n & 1) && !(ldq & 1) && !((uintptr_t)Q & 15)) {
-    // rows r, r + 1 (r even) in one 16-byte load per column
-    for (int r = 2 * threadIdx.x; r < n; r += 512) {
-      double k0[K], k1[K];
+    // rows r, r + 1 (r even) in one 16-byte load per column; two such pairs,
+    // 512 rows apart, per step
+    typedef double dv2 __attribute__((ext_vector_type(2)));
+    for (int r0 = 2 * threadIdx.x; r0 < n; r0 += 1024) {
+      dv2 v[2][CPB];
 #pragma unroll
-      for (int c = 0; c < K; ++c) {
-        k0[c] = Km[r + (size_t)c * w.ldk];
-        k1[c] = Km[r + 1 + (size_t)c * w.ldk];
-      }
+      for (int h = 0; h < 2; ++h)
 #pragma unroll
-      for (int q = 0; q < CPB; ++q) {
-        double2 v = make_double2(0.0, 0.0);
-        if (q < ncol) v = *reinterpret_cast<const double2*>(Q + r + (size_t)(j0 + q) * ldq);
+        for (int q = 0; q < CPB; ++q) {
+          const int r = r0 + 512 * h;
+          v[h][q] = dv2{0.0, 0.0};
+          if (q < ncol && r < n)
+            v[h][q] = __builtin_nontemporal_load(
+                reinterpret_cast<const dv2*>(Q + r + (size_t)(j0 + q) * ldq));
+        }
 #pragma unroll
-        for (int c = 0; c < K; ++c) acc[q][c] = fma(v.y, k1[c], fma(v.x, k0[c], acc[q][c]));
+      for (int h = 0; h < 2; ++h) {
+        const int r = r0 + 512 * h;
+        if (r >= n) break;
+        double k0[K], k1[K];
+#pragma unroll
+        for (int c = 0; c < K; ++c) {
+          k0[c] = Km[r + (size_t)c * w.ldk];
+          k1[c] = Km[r + 1 + (size_t)c * w.ldk];
+        }
+#pragma unroll
+        for (int q = 0; q < CPB; ++q)
+#pragma unroll
+          for (int c = 0; c < K; ++c)
+            acc[q][c] = fma(v[h][q][1], k1[c], fma(v[h][q][0], k0[c], acc[q][c]));
       }
     }
   } else {
@@ -88,7 +107,7 @@ __global__ __launch_bounds__(256) void qtk_group(Group g) {
   qtk_body<K, CPB>(g.works[i], blockIdx.x - g.prefix[i]);
 }
 
-constexpr int qtk_cpb(int k) { return (k <= 2) ? 8 : 4; }
+constexpr int qtk_cpb(int) { return 2; }
 
 int qtk_blocks(int n, int k) { return (n + qtk_cpb(k) - 1) / qtk_cpb(k); }
 
