@@ -578,6 +578,131 @@ __global__ __launch_bounds__(LNT, 1) void gemm_lp_kernel(int n, const void* __re
     }
 }
 
+// The BF16X3 product when n is a multiple of RG_BK: the same slices, products,
+// order and promotions as gemm_lp_kernel (bitwise the same C), staged through a
+// three-stage LDS ring that the global -> LDS loads (global_load_lds_dwordx4,
+// no registers) fill two slices ahead of the MFMAs.  128 x 128 block tile, 8
+// waves of 64 x 32 (two waves per SIMD, so one wave's FP64 promotion and waits
+// overlap the other's MFMAs).  Each tile row of a plane is 4 chunks of 16 bytes
+// (32 k); chunk kc of row r sits at position kc ^ ((r >> 1) & 3), which puts
+// the 8 rows an 8-lane group reads at distinct 16-byte bank groups.  Rows past
+// n are read from row n - 1 (their outputs are not stored); n % RG_BK == 0
+// keeps every k in range.  The loads are not tracked by the compiler's waits:
+// before the barrier that opens a slice, each wave waits (vmcnt) until only the
+// loads of the later slices are outstanding, and the barrier that closes it
+// keeps a stage from being refilled while a wave still reads it.
+constexpr int RG_BK = 32;     // k per stage: one MFMA deep
+constexpr int RG_STAGES = 3;  // slices kt + 1 and kt + 2 load while slice kt is multiplied
+constexpr int RG_NT = 512;
+
+typedef __attribute__((address_space(3))) void* lds_void_ptr;
+
+__global__ __launch_bounds__(RG_NT, 1) void gemm_bf16x3_ring(int n,
+                                                           const unsigned short* __restrict__ Qs,
+                                                           const unsigned short* __restrict__ Ws,
+                                                           double* __restrict__ C,
+                                                           const int32_t* status, int tiles) {
+  if (__builtin_nontemporal_load(status) != 0) return;
+  // [stage][operand: Q, W][plane][tile row][k]: 16-byte chunks, the 4 chunks of a
+  // row stored at position kc ^ ((row >> 1) & 3)
+  __shared__ __attribute__((aligned(16))) unsigned short L[RG_STAGES][2][3][LBM][RG_BK];
+  int tm, tn;
+  lp_tile_of(blockIdx.x, tiles, tiles, &tm, &tn);
+  const int m0 = tm * LBM, n0 = tn * LBN;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int wm = (wv & 1) * 64, wn = (wv >> 1) * 32;
+  const size_t nn = (size_t)n * n;
+  // one stage: per operand 3 planes x 128 rows x 4 chunks; instruction i of wave
+  // wv loads chunks i * 512 + 64 wv + lane (one plane, 16 rows)
+  auto issue = [&](int kt, int stg) {
+    const int k0 = kt * RG_BK;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      const int c0 = i * 512 + wv * 64;
+      const int s = c0 >> 9, row0 = (c0 & 511) >> 2;
+      const int row = row0 + (lane >> 2), kcs = lane & 3;
+      const int kc = kcs ^ ((row >> 1) & 3);
+      const int ga = min(m0 + row, n - 1), gb = min(n0 + row, n - 1);
+      __builtin_amdgcn_global_load_lds(Qs + s * nn + (size_t)ga * n + k0 + 8 * kc,
+                                       (lds_void_ptr)&L[stg][0][s][row0][0], 16, 0, 0);
+      __builtin_amdgcn_global_load_lds(Ws + s * nn + (size_t)gb * n + k0 + 8 * kc,
+                                       (lds_void_ptr)&L[stg][1][s][row0][0], 16, 0, 0);
+    }
+  };
+  d4 accD[4][2];
+  f4 acc[4][2];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      accD[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+      acc[i][j] = f4{0.0f, 0.0f, 0.0f, 0.0f};
+    }
+  const int nk = n / RG_BK;
+  const int fr = lane & 15, fg = lane >> 4;
+  issue(0, 0);
+  if (nk > 1) issue(1, 1);
+  for (int kt = 0; kt < nk; ++kt) {
+    const int cur = kt % RG_STAGES;
+    // stage (kt + 2) % 3 was last read in step kt - 1, before its closing barrier
+    if (kt + 2 < nk) {
+      issue(kt + 2, (kt + 2) % RG_STAGES);
+      asm volatile("s_waitcnt vmcnt(12)" ::: "memory");
+    } else if (kt + 1 < nk) {
+      asm volatile("s_waitcnt vmcnt(6)" ::: "memory");
+    } else {
+      asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    }
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
+    bf8 a[3][4], b[3][2];
+#pragma unroll
+    for (int s = 0; s < 3; ++s) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int r = wm + i * 16 + fr;
+        a[s][i] = *reinterpret_cast<const bf8*>(&L[cur][0][s][r][8 * (fg ^ ((r >> 1) & 3))]);
+      }
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        const int r = wn + j * 16 + fr;
+        b[s][j] = *reinterpret_cast<const bf8*>(&L[cur][1][s][r][8 * (fg ^ ((r >> 1) & 3))]);
+      }
+    }
+    constexpr int PA[6] = {2, 1, 0, 1, 0, 0}, PB[6] = {0, 1, 2, 0, 1, 0};
+#pragma unroll
+    for (int p = 0; p < 6; ++p)
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[PA[p]][i], b[PB[p]][j], acc[i][j], 0, 0, 0);
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) accD[i][j][v] += (double)acc[i][j][v];
+        acc[i][j] = f4{0.0f, 0.0f, 0.0f, 0.0f};
+      }
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_s_barrier();
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int col = n0 + wn + j * 16 + fr;
+      if (col >= n) continue;
+      double* dst = C + (size_t)col * n;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = m0 + wm + i * 16 + 4 * fg + v;
+        if (row < n) dst[row] = accD[i][j][v];
+      }
+    }
+}
+
 size_t lp_plane_bytes(int prec, int n) {
   const size_t nn = (size_t)n * n;
   size_t b = 0;
@@ -600,8 +725,13 @@ static hipError_t gemm_lp_launch(const Work& w, void* qplanes, void* wplanes, hi
                      st);
   if (hipGetLastError() != hipSuccess) return hipErrorLaunchFailure;
   const int tiles = (n + LBM - 1) / LBM;
-  hipLaunchKernelGGL((gemm_lp_kernel<P>), dim3(tiles * tiles), dim3(LNT), 0, s, n,
-                     (const void*)qplanes, (const void*)wplanes, w.Q_out, st, tiles);
+  if (P == EIG_GEMM_BF16X3_CORR && n % RG_BK == 0)
+    hipLaunchKernelGGL(gemm_bf16x3_ring, dim3(tiles * tiles), dim3(RG_NT), 0, s, n,
+                       static_cast<const unsigned short*>(qplanes),
+                       static_cast<const unsigned short*>(wplanes), w.Q_out, st, tiles);
+  else
+    hipLaunchKernelGGL((gemm_lp_kernel<P>), dim3(tiles * tiles), dim3(LNT), 0, s, n,
+                       (const void*)qplanes, (const void*)wplanes, w.Q_out, st, tiles);
   return hipGetLastError();
 }
 
