@@ -634,10 +634,7 @@ __global__ __launch_bounds__(RG_NT, 1) void gemm_bf16x3_ring(int n,
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j) {
-      accD[i][j] = d4{0.0, 0.0, 0.0, 0.0};
-      acc[i][j] = f4{0.0f, 0.0f, 0.0f, 0.0f};
-    }
+    for (int j = 0; j < 2; ++j) accD[i][j] = d4{0.0, 0.0, 0.0, 0.0};
   const int nk = n / RG_BK;
   const int fr = lane & 15, fg = lane >> 4;
   issue(0, 0);
@@ -669,9 +666,16 @@ __global__ __launch_bounds__(RG_NT, 1) void gemm_bf16x3_ring(int n,
         b[s][j] = *reinterpret_cast<const bf8*>(&L[cur][1][s][r][8 * (fg ^ ((r >> 1) & 3))]);
       }
     }
+    // the slice's FP32 partial sums start from zero in the first product
     constexpr int PA[6] = {2, 1, 0, 1, 0, 0}, PB[6] = {0, 1, 2, 0, 1, 0};
 #pragma unroll
-    for (int p = 0; p < 6; ++p)
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[PA[0]][i], b[PB[0]][j],
+                                                            f4{0.0f, 0.0f, 0.0f, 0.0f}, 0, 0, 0);
+#pragma unroll
+    for (int p = 1; p < 6; ++p)
 #pragma unroll
       for (int i = 0; i < 4; ++i)
 #pragma unroll
@@ -680,11 +684,9 @@ __global__ __launch_bounds__(RG_NT, 1) void gemm_bf16x3_ring(int n,
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
-      for (int j = 0; j < 2; ++j) {
+      for (int j = 0; j < 2; ++j)
 #pragma unroll
         for (int v = 0; v < 4; ++v) accD[i][j][v] += (double)acc[i][j][v];
-        acc[i][j] = f4{0.0f, 0.0f, 0.0f, 0.0f};
-      }
     asm volatile("" ::: "memory");
     __builtin_amdgcn_s_barrier();
   }

@@ -2,14 +2,14 @@
 //
 // Q is n-by-n column-major (leading dimension ldq >= n) and K n-by-k with
 // k <= 8, so U is a skinny product bound by streaming Q from HBM once
-// (8 n^2 bytes, 2 n^2 k flops).  A block of 256 threads owns CPB = 2
-// consecutive columns of Q: each thread takes the row pairs r = 2 tid + 1024 i
-// and r + 512 (16-byte streaming loads, coalesced along the column, all four
-// issued before any is used; rows tid, tid + 256, ... when n or ldq is odd),
-// combines them with K's rows, and the block reduces CPB*k partial sums at the
-// end.  Few columns per block keep the concurrent streams of a CU close
-// together in memory; measured at n = 8192 this runs at the read-only streaming
-// rate of the chip (more columns per block, or one pair per thread, did not).
+// (8 n^2 bytes, 2 n^2 k flops).  A block of 256 threads owns CPB consecutive
+// columns of Q (qtk_cpb: 2 to 8 with k): each thread takes the row pairs
+// r = 2 tid + 1024 i and r + 512 (16-byte streaming loads, coalesced along the
+// column, all issued before any is used; rows tid, tid + 256, ... when n or ldq
+// is odd), combines them with K's rows, and the block reduces CPB*k partial
+// sums at the end.  Measured at n = 8192, k = 2 this runs within 5% of the
+// read-only streaming rate of the chip (eight columns per block and one row
+// pair per step: 20% slower).
 // Non-finite entries of U raise the sticky ST_NONFINITE bit.
 #include "common.h"
 
@@ -107,7 +107,10 @@ __global__ __launch_bounds__(256) void qtk_group(Group g) {
   qtk_body<K, CPB>(g.works[i], blockIdx.x - g.prefix[i]);
 }
 
-constexpr int qtk_cpb(int) { return 2; }
+// Columns per block: each thread loads k entries of K per row pair and uses them
+// for CPB columns, so CPB grows with k; measured at n = 8192 and 16384 (k = 1:
+// 2; k = 2: 4; k >= 3: 8, within 2% of the best of {2, 4, 8} at both sizes).
+constexpr int qtk_cpb(int k) { return (k == 1) ? 2 : (k == 2) ? 4 : 8; }
 
 int qtk_blocks(int n, int k) { return (n + qtk_cpb(k) - 1) / qtk_cpb(k); }
 
