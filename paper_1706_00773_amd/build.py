@@ -18,7 +18,7 @@ BUILD_DIR = os.path.join(ROOT, "_build")
 
 SOURCES = ["api.hip", "batch.hip", "server.hip", "qtk.hip", "deflate.hip", "secular.hip",
            "vectors.hip", "gemm.hip", "precision.hip", "chain.hip", "farfield.hip", "noalloc.hip",
-           "checks.hip"]
+           "checks.hip", "subset.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

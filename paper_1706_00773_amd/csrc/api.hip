@@ -550,8 +550,15 @@ int eig_update_interval(eig_state_t s, int64_t k, const double* K, int64_t ldk,
   if (!vo) {
     HIPCHK(launch_wbuild(w, st));
     HIPCHK(launch_group_reflect(w, st));
-    HIPCHK(launch_dgemm((int)n, (int)m, (int)n, w.Q_in, (int)n, w.W, (int)n, V_out, (int)ldv,
-                        &w.st->status, st));
+    // a few columns: the split-k product on the vector units, its partial sums
+    // in the spare n x n buffer (nothing is committed here)
+    if (skinny_applies((int)n, (int)m, w.Q_in, (int)n) &&
+        skinny_workspace((int)n, (int)m) <= n * n * sizeof(double))
+      HIPCHK(launch_skinny_qw((int)n, (int)m, w.Q_in, (int)n, w.W, (int)n, V_out, (int)ldv,
+                              w.Q_out, &w.st->status, st));
+    else
+      HIPCHK(launch_dgemm((int)n, (int)m, (int)n, w.Q_in, (int)n, w.W, (int)n, V_out, (int)ldv,
+                          &w.st->status, st));
   }
   HIPCHK(hipStreamSynchronize(st));
   HIPCHK(hipMemcpy(&ds, s->w.st, sizeof(ds), hipMemcpyDeviceToHost));

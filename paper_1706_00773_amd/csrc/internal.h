@@ -265,6 +265,14 @@ hipError_t launch_perturb_w(const Work& w, double* lam_out, hipStream_t s);
 hipError_t launch_dgemm(int M, int N, int Kd, const double* A, int lda, const double* B, int ldb,
                         double* C, int ldc, const int32_t* status, hipStream_t s);
 // Segmented products from ninst device-built descriptors (tiles as below).
+// V = Q W for m <= 128 columns (subset.hip): split-k partial sums in `part`
+// (skinny_workspace bytes), then their ordered sum; needs n and ldq even and Q
+// 16-byte aligned (skinny_applies).
+size_t skinny_workspace(int n, int m);
+bool skinny_applies(int n, int m, const double* Q, int ldq);
+hipError_t launch_skinny_qw(int n, int m, const double* Q, int ldq, const double* W, int ldw,
+                            double* V, int ldv, double* part, const int32_t* status,
+                            hipStream_t s);
 hipError_t launch_dgemm_seg(const GemmSegDesc* d, const int* prefix, int ninst, int blocks,
                             const int32_t* skip, hipStream_t s);
 // Products from ninst device-built descriptors (acc: C += A B) on bt x bt tiles

@@ -80,6 +80,26 @@ def test_interval_matches_oracle(n, k, frac):
     _check_subset(u, a, b, lam.cpu().numpy(), V.cpu().numpy())
 
 
+@pytest.mark.parametrize("n,m", [(1024, 1), (1024, 8), (1024, 9), (1024, 17), (1024, 33),
+                                 (1024, 64), (1024, 65), (1024, 128), (1024, 129), (1023, 20),
+                                 (8192, 40)])
+def test_interval_eigenvector_widths(n, m):
+    """Exactly m eigenvalues in [a, b): with n even and m <= 128 the vectors come
+    from the split-k product on the vector units (partial sums per 128 k, added
+    in order), otherwise from the MFMA GEMM; both against the oracle."""
+    print(f"case interval widths n={n} m={m}", flush=True)
+    u = wl.random_small(n, 2, seed=700 + m, knorm=1.5) if n <= 1024 else wl.general_rankk(2, n=n, seed=701)
+    Q = np.asfortranarray(np.asarray(u.Q))
+    ref, _, _ = oracle.update(u.lam, Q, u.K, u.sigma, values_only=True)
+    i0 = n // 3
+    a = 0.5 * (ref[i0 - 1] + ref[i0])
+    b = 0.5 * (ref[i0 + m - 1] + ref[i0 + m])
+    with _state(u) as s:
+        lam, V = s.interval(colmajor(u.K, "cuda:0"), u.sigma, a, b, m_max=m)
+    assert lam.numel() == m
+    _check_subset(u, a, b, lam.cpu().numpy(), V.cpu().numpy())
+
+
 def test_whole_line_equals_full_update():
     import torch
 
