@@ -92,6 +92,11 @@ struct eig_batch_s {
   int slot = 0;
   hipStream_t cap = nullptr;
   hipEvent_t tev[4] = {};
+  // the per-rank chains of a batch with several ranks run on side streams,
+  // forked from and joined back into the caller's stream
+  hipStream_t side[KMAX + 1] = {};
+  hipEvent_t fork_ev = nullptr;
+  hipEvent_t join_ev[KMAX + 1] = {};
   struct Entry {
     int seen = 0;
     hipGraphExec_t exec = nullptr;
@@ -154,29 +159,83 @@ hipError_t enqueue(eig_batch_s* b, const Plan& p, bool vo, int root_form, int ti
     e = (x);               \
     if (e != hipSuccess) return e; \
   } while (0)
-  for (int k = 1; k <= KMAX; ++k)
-    if (p.cnt[k]) STEP(launch_qtk_group(k, group(k, KIND_QTK), p.blocks[k][KIND_QTK], st));
-  for (int k = 1; k <= KMAX; ++k)
-    if (p.cnt[k]) STEP(launch_deflate_group(k, d_works + p.off[k], p.cnt[k], st));
-  for (int k = 1; k <= KMAX; ++k)
-    if (p.cnt[k]) STEP(launch_polecount_group(k, group(k, KIND_ROOT), p.blocks[k][KIND_ROOT], st));
-  for (int k = 1; k <= KMAX; ++k)
-    if (p.cnt[k]) STEP(launch_locate_group(d_works + p.off[k], p.cnt[k], st));
-  if (ev) STEP(hipEventRecord(ev[0], st));
+  // one rank's phases up to W (the instances of different ranks share nothing
+  // until the grouped GEMM)
   const int pgrid = (root_form == EIG_ROOTSOLVE_PERSISTENT) ? 2 * b->num_cu : 0;
-  for (int k = 1; k <= KMAX; ++k)
-    if (p.cnt[k])
-      STEP(launch_rootsolve_group(k, group(k, KIND_SOLVE), p.blocks[k][KIND_SOLVE],
-                                  group(k, KIND_ROOT), p.blocks[k][KIND_ROOT], pgrid,
-                                  b->d_queue + k, st));
-  if (ev) STEP(hipEventRecord(ev[1], st));
-  for (int k = 1; k <= KMAX; ++k)
-    if (p.cnt[k]) STEP(launch_finalize_group(k, d_works + p.off[k], p.cnt[k], st));
-  if (vo) return hipSuccess;
-  for (int k = 1; k <= KMAX; ++k)
-    if (p.cnt[k]) STEP(launch_wbuild_group(k, group(k, KIND_WB), p.blocks[k][KIND_WB], st));
-  for (int k = 1; k <= KMAX; ++k)
-    if (p.cnt[k]) STEP(launch_reflect_group(k, group(k, KIND_REFL), p.blocks[k][KIND_REFL], st));
+  auto chain = [&](int k, hipStream_t cs, bool timed) -> hipError_t {
+    hipError_t e2;
+#define CSTEP(x)                      \
+  do {                                \
+    e2 = (x);                         \
+    if (e2 != hipSuccess) return e2;  \
+  } while (0)
+    CSTEP(launch_qtk_group(k, group(k, KIND_QTK), p.blocks[k][KIND_QTK], cs));
+    CSTEP(launch_deflate_group(k, d_works + p.off[k], p.cnt[k], cs));
+    CSTEP(launch_polecount_group(k, group(k, KIND_ROOT), p.blocks[k][KIND_ROOT], cs));
+    CSTEP(launch_locate_group(d_works + p.off[k], p.cnt[k], cs));
+    if (timed) CSTEP(hipEventRecord(ev[0], cs));
+    CSTEP(launch_rootsolve_group(k, group(k, KIND_SOLVE), p.blocks[k][KIND_SOLVE],
+                                 group(k, KIND_ROOT), p.blocks[k][KIND_ROOT], pgrid,
+                                 b->d_queue + k, cs));
+    if (timed) CSTEP(hipEventRecord(ev[1], cs));
+    CSTEP(launch_finalize_group(k, d_works + p.off[k], p.cnt[k], cs));
+    if (vo) return hipSuccess;
+    CSTEP(launch_wbuild_group(k, group(k, KIND_WB), p.blocks[k][KIND_WB], cs));
+    CSTEP(launch_reflect_group(k, group(k, KIND_REFL), p.blocks[k][KIND_REFL], cs));
+#undef CSTEP
+    return hipSuccess;
+  };
+  int ranks = 0;
+  for (int k = 1; k <= KMAX; ++k) ranks += p.cnt[k] ? 1 : 0;
+  if (ev || ranks < 2) {
+    // one stream, phase by phase across the ranks (the autotuner's timed runs
+    // bracket the root solve of all ranks with its events)
+    for (int k = 1; k <= KMAX; ++k)
+      if (p.cnt[k]) STEP(launch_qtk_group(k, group(k, KIND_QTK), p.blocks[k][KIND_QTK], st));
+    for (int k = 1; k <= KMAX; ++k)
+      if (p.cnt[k]) STEP(launch_deflate_group(k, d_works + p.off[k], p.cnt[k], st));
+    for (int k = 1; k <= KMAX; ++k)
+      if (p.cnt[k])
+        STEP(launch_polecount_group(k, group(k, KIND_ROOT), p.blocks[k][KIND_ROOT], st));
+    for (int k = 1; k <= KMAX; ++k)
+      if (p.cnt[k]) STEP(launch_locate_group(d_works + p.off[k], p.cnt[k], st));
+    if (ev) STEP(hipEventRecord(ev[0], st));
+    for (int k = 1; k <= KMAX; ++k)
+      if (p.cnt[k])
+        STEP(launch_rootsolve_group(k, group(k, KIND_SOLVE), p.blocks[k][KIND_SOLVE],
+                                    group(k, KIND_ROOT), p.blocks[k][KIND_ROOT], pgrid,
+                                    b->d_queue + k, st));
+    if (ev) STEP(hipEventRecord(ev[1], st));
+    for (int k = 1; k <= KMAX; ++k)
+      if (p.cnt[k]) STEP(launch_finalize_group(k, d_works + p.off[k], p.cnt[k], st));
+    if (vo) return hipSuccess;
+    for (int k = 1; k <= KMAX; ++k)
+      if (p.cnt[k])
+        STEP(launch_wbuild_group(k, group(k, KIND_WB), p.blocks[k][KIND_WB], st));
+    for (int k = 1; k <= KMAX; ++k)
+      if (p.cnt[k])
+        STEP(launch_reflect_group(k, group(k, KIND_REFL), p.blocks[k][KIND_REFL], st));
+  } else {
+    // several ranks: the first rank's chain on `st`, the others on side
+    // streams forked from it, all joined back before the grouped GEMM (inside
+    // a capture the side streams join the graph through the fork event)
+    STEP(hipEventRecord(b->fork_ev, st));
+    int first = 0;
+    for (int k = 1; k <= KMAX; ++k) {
+      if (!p.cnt[k]) continue;
+      if (!first) {
+        first = k;
+        continue;
+      }
+      STEP(hipStreamWaitEvent(b->side[k], b->fork_ev, 0));
+      STEP(chain(k, b->side[k], false));
+      STEP(hipEventRecord(b->join_ev[k], b->side[k]));
+    }
+    STEP(chain(first, st, false));
+    for (int k = first + 1; k <= KMAX; ++k)
+      if (p.cnt[k]) STEP(hipStreamWaitEvent(st, b->join_ev[k], 0));
+    if (vo) return hipSuccess;
+  }
   if (ev) STEP(hipEventRecord(ev[2], st));
   STEP(launch_dgemm_group(tile, d_gemm, d_prefix + p.gemm_poff, p.count, p.gemm_blocks, st));
   // instances of the far-field product: their own plan, W blocks and products
@@ -229,6 +288,10 @@ int eig_batch_create(eig_batch_t* out, int32_t max_items, int32_t device) {
          hipEventCreateWithFlags(&b->slot_ev[i], hipEventDisableTiming) == hipSuccess;
   for (int i = 0; ok && i < 4; ++i) ok = hipEventCreate(&b->tev[i]) == hipSuccess;
   ok = ok && hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking) == hipSuccess;
+  ok = ok && hipEventCreateWithFlags(&b->fork_ev, hipEventDisableTiming) == hipSuccess;
+  for (int k = 1; ok && k <= KMAX; ++k)
+    ok = hipStreamCreateWithFlags(&b->side[k], hipStreamNonBlocking) == hipSuccess &&
+         hipEventCreateWithFlags(&b->join_ev[k], hipEventDisableTiming) == hipSuccess;
   if (!ok) {
     (void)hipGetLastError();
     eig_batch_destroy(b);
@@ -253,6 +316,11 @@ int eig_batch_destroy(eig_batch_t b) {
     for (auto& h : b->h_slot)
       if (h) (void)hipHostFree(h);
     if (b->cap) (void)hipStreamDestroy(b->cap);
+    for (int k = 1; k <= KMAX; ++k) {
+      if (b->side[k]) (void)hipStreamDestroy(b->side[k]);
+      if (b->join_ev[k]) (void)hipEventDestroy(b->join_ev[k]);
+    }
+    if (b->fork_ev) (void)hipEventDestroy(b->fork_ev);
     if (b->d_block) (void)hipFree(b->d_block);
   }
   delete b;
