@@ -13,13 +13,19 @@
 //      (value: the group's first pole); the other m - r rows are deflated;
 //   4. compaction (block prefix sums) into the reduced arrays, segments and the
 //      deflated list, all in ascending pole order.
-// One block of 1024 threads; groups of two or more rows are rare and each is
+// One block (1024 threads, 512 from k = 5); groups of two or more rows are rare and each is
 // factorised by one thread.
 #include "common.h"
 
 namespace eigupd {
 
-constexpr int DNT = 1024;
+// Threads of the deflation block: 1024 up to k = 4, 512 from k = 5.  A 1024-thread
+// block allows 128 VGPRs; from k = 3 the per-thread rows of U spill there
+// (15 VGPRs at k = 3, 190 at k = 8).  Measured at n = 8192: 512 threads cost
+// k = 4 24 us (99 -> 123 us; half the waves to hide latency) and saved k = 8
+// 15 us (181 -> 166 us).
+template <int K>
+constexpr int dnt() { return (K <= 4) ? 1024 : 512; }
 
 template <int K>
 __device__ void group_qr(const Work& w, int g, double tol_abs, double* rem2) {
@@ -78,6 +84,7 @@ __device__ void group_qr(const Work& w, int g, double tol_abs, double* rem2) {
 
 template <int K>
 __device__ __forceinline__ void deflate_body(const Work& w) {
+  constexpr int DNT = dnt<K>();
   __shared__ double shd[DNT / 64 + 1];
   __shared__ int shi[DNT / 64 + 1];
   __shared__ int s_bad;
@@ -291,19 +298,19 @@ __device__ __forceinline__ void deflate_body(const Work& w) {
 }
 
 template <int K>
-__global__ __launch_bounds__(DNT) void deflate_kernel(Work w) {
+__global__ __launch_bounds__(dnt<K>()) void deflate_kernel(Work w) {
   deflate_body<K>(w);
 }
 
 // one block per instance
 template <int K>
-__global__ __launch_bounds__(DNT) void deflate_group(const Work* __restrict__ works) {
+__global__ __launch_bounds__(dnt<K>()) void deflate_group(const Work* __restrict__ works) {
   deflate_body<K>(works[blockIdx.x]);
 }
 
 template <int K>
 static hipError_t deflate_group_launch(const Work* works, int ninst, hipStream_t s) {
-  hipLaunchKernelGGL((deflate_group<K>), dim3(ninst), dim3(DNT), 0, s, works);
+  hipLaunchKernelGGL((deflate_group<K>), dim3(ninst), dim3(dnt<K>()), 0, s, works);
   return hipGetLastError();
 }
 
@@ -314,7 +321,7 @@ hipError_t launch_deflate_group(int k, const Work* works, int ninst, hipStream_t
 
 template <int K>
 static hipError_t deflate_launch(const Work& w, hipStream_t s) {
-  hipLaunchKernelGGL((deflate_kernel<K>), dim3(1), dim3(DNT), 0, s, w);
+  hipLaunchKernelGGL((deflate_kernel<K>), dim3(1), dim3(dnt<K>()), 0, s, w);
   return hipGetLastError();
 }
 
