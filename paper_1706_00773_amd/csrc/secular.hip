@@ -44,7 +44,10 @@ constexpr double EPSU = 1.1102230246251565e-16;  // 2^-53
 template <int K>
 struct Cfg {
   static constexpr int NS = K * (K + 1) / 2;
-  static constexpr int WV = (K <= 1) ? 16 : (K <= 3) ? 8 : (K <= 4) ? 4 : 2;
+  // waves per block: from rank 4 a wave holds one SIMD (above 128 VGPRs), so 4
+  // waves fill a CU's SIMDs (2 waves at ranks 5-8 left half of them idle: pole
+  // counts and roots 1.5-1.8x slower at n = 8192)
+  static constexpr int WV = (K <= 1) ? 16 : (K <= 3) ? 8 : 4;
   static constexpr int RPB = 32;          // roots (or poles) per block
   static constexpr int SPLIT = 64 / RPB;  // parts of a wave sharing one root
   static constexpr int TP = 128;          // poles per LDS tile per wave
@@ -370,8 +373,6 @@ constexpr double QUAD_R = 1e-3;
 // slowest of a fixed set of roots has converged.
 template <int K>
 struct RsCfg {
-  // ranks >= 5 carry k(k+1) accumulators per lane: 4 waves of smaller tiles and
-  // a shallower unroll keep them in 256 VGPRs (two waves per SIMD)
   static constexpr int WV = Cfg<K>::WV;
   static constexpr int RPB = 8;
   static constexpr int SPLIT = 64 / RPB;
