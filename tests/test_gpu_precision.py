@@ -18,7 +18,9 @@ What each mode must deliver:
 - Residual and orthogonality: ||dq||_2 <= sqrt(n) QW_TOL per column gives
   ||A'q - lambda q|| <= 2 sqrt(n) QW_TOL ||A'|| and |q_i^T q_j - delta_ij| <=
   2 sqrt(n) QW_TOL.
-The measured errors are printed for the record.
+The measured errors are printed for the record.  n a multiple of 32 (64, 544,
+1056) runs the BF16X3 product through its LDS-ring kernel, with partial tiles
+at 544 and 1056.
 """
 import math
 
@@ -50,7 +52,7 @@ def _gpu():
 
 @pytest.mark.parametrize("mode", list(MODES))
 @pytest.mark.parametrize("n,k,seed", [(300, 4, 11), (301, 2, 12), (257, 8, 13), (64, 1, 14),
-                                      (515, 3, 15)])
+                                      (515, 3, 15), (544, 4, 16), (1056, 2, 17)])
 def test_reduced_precision_vs_oracle(mode, n, k, seed):
     print(f"case mode={mode} n={n} k={k} seed={seed}", flush=True)
     u = wl.logspread_rankk(k, n=n, seed=seed)
