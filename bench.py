@@ -583,18 +583,35 @@ def measured_traffic(path_name, sources):
 
 
 # Block size and Chebyshev nodes of the library's far-field product (farfield.hip).
-FF_B, FF_P = 256, 24
+FF_B = 256  # columns per column block of the far-field product
+
+
+def farfield_cfg(k):
+    """Rows per row block and nodes per row / column interval of the far-field plan
+    (half-width row blocks up to rank 2)."""
+    return (128, 22, 24) if k <= 2 else (256, 24, 24)
 
 
 def farfield_flops(n, k):
-    """Algorithmic flops of Q W by the far-field product: the exact band of row
-    blocks I-1..I+1 per column block, P2M (2 n^2 kP), M2L (2 kn (nb P)^2) and L2P
-    (2 n^2 kP).  The extra near pairs the plan may add are not counted."""
-    nb = n // FF_B
-    size = [FF_B] * (nb - 1) + [n - (nb - 1) * FF_B]
-    band = sum(2.0 * n * size[i] * sum(size[max(0, i - 1):min(nb, i + 2)]) for i in range(nb))
-    kp = k * FF_P
-    return band + 2.0 * n * n * kp + 2.0 * k * n * (nb * FF_P) ** 2 + 2.0 * n * n * kp
+    """Algorithmic flops of Q W by the far-field product: per column block of 256
+    the exact rows within one row block of it (the band), P2M (2 n^2 k pr), M2L
+    (2 k n (nr pr)(nb pc)) and L2P (2 n^2 k pc).  The rows the plan adds for
+    blocks widened by outlying poles or roots are not counted."""
+    rb, pr, pc = farfield_cfg(k)
+    nb, nr = n // FF_B, n // rb
+    rpc = FF_B // rb
+
+    def rows(lo, hi):
+        return (n if hi + 1 >= nr else (hi + 1) * rb) - lo * rb
+
+    band = 0.0
+    for i in range(nb):
+        b = FF_B if i + 1 < nb else n - (nb - 1) * FF_B
+        lo = max(0, i * rpc - 1)
+        hi = nr - 1 if i + 1 == nb else min(nr - 1, (i + 1) * rpc)
+        band += 2.0 * n * b * rows(lo, hi)
+    return (band + 2.0 * n * n * k * pr + 2.0 * k * n * (nr * pr) * (nb * pc)
+            + 2.0 * n * n * k * pc)
 
 
 def main():

@@ -444,7 +444,7 @@ int eig_update_batch(eig_batch_t b, const eig_batch_item* items, int32_t count, 
     const eig_batch_item& it = items[p.order[pos]];
     eig_state_s* s = it.state;
     if (!want_ff || !ff_eligible((int)s->n, (int)it.k)) continue;
-    const size_t need = ff_bytes((int)s->n, KMAX);
+    const size_t need = ff_bytes_max((int)s->n);
     if (s->ff_bytes < need) {
       if (s->ff_block) {
         HIPCHK(hipDeviceSynchronize());

@@ -206,25 +206,41 @@ struct GemmSegDesc {
 // Q' = Q W with the far blocks of W from Chebyshev expansions (farfield.hip):
 // buffers of one state, laid out by ff_layout in ff_bytes(n, k) bytes.
 struct FarField {
-  int n, k, nb, pad;
-  double* M;      // (k n) x (nb P) expansions of the row blocks
-  double* L;      // (k n) x (nb P) expansions at the column blocks
-  double* T;      // (nb P) x (nb P) interaction matrix
-  double* B;      // row-block weights, b_J x kP each
-  double* Phi;    // kP x n column weights
-  double* iv;     // 4 per block: pole interval, column-point interval
-  double* xn;     // nb P column-block nodes
-  double* yn;     // nb P row-block nodes
-  GemmDescG* desc;    // nb: P2M
-  GemmSegDesc* seg;   // nb: band + extra near pairs + L2P of each column block
-  int* prefix;        // 2 (nb + 1) tile offsets: P2M, segmented products
-  int* near;      // 2 nb: first and last row block of each near band
-  int* extra;     // 4 nb: row blocks of the extra near pairs of each column block (-1: none)
+  int n, k, nb, nr;     // column blocks of 256 columns, row blocks of rb rows
+  int rb, pr, pc, pad;  // row block size; nodes per row / column interval
+  double etar, etac;    // far: distance >= etac column width and >= etar row width
+  double* M;      // (k n) x (nr pr) expansions of the row blocks
+  double* L;      // (k n) x (nb pc) expansions at the column blocks
+  double* T;      // (nr pr) x (nb pc) interaction matrix
+  double* B;      // row-block weights, b_h x k pr each
+  double* Phi;    // k pc x n column weights
+  double* ivr;    // 2 per row block: pole interval
+  double* ivc;    // 2 per column block: column-point interval
+  double* xn;     // nb pc column-block nodes
+  double* yn;     // nr pr row-block nodes
+  GemmDescG* desc;    // nr: P2M
+  GemmSegDesc* seg;   // nb: near rows + L2P of each column block, in launch order
+  int* prefix;        // (nr + 1) + (nb + 1) tile offsets: P2M, segmented products
+  int* near;      // 2 nb: first and last row block of each band
+  int* extra;     // 2 (GSEG - 2) nb: further near row-block ranges [lo, hi] (lo < 0: none)
   int* flags;     // [0] far path skipped, [1] dense path skipped
 };
+// Rows [ff_row_begin, ff_row_end) of row block h (the last block takes the rest).
+__host__ __device__ inline int ff_row_begin(const FarField& f, int h) { return h * f.rb; }
+__host__ __device__ inline int ff_row_end(const FarField& f, int h) {
+  return h + 1 >= f.nr ? f.n : (h + 1) * f.rb;
+}
+// Row block h is multiplied exactly for column block I (band or further range).
+__device__ inline bool ff_near(const FarField& f, int I, int h) {
+  bool nr = h >= f.near[2 * I] && h <= f.near[2 * I + 1];
+  for (int r = 0; r < GSEG - 2; ++r)
+    nr = nr || (h >= f.extra[2 * (I * (GSEG - 2) + r)] && h <= f.extra[2 * (I * (GSEG - 2) + r) + 1]);
+  return nr;
+}
 bool ff_eligible(int n, int k);
 int ff_blocks(int n);
 size_t ff_bytes(int n, int k);
+size_t ff_bytes_max(int n);  // the most ff_bytes(n, k) over every rank
 FarField ff_layout(void* base, int n, int k);
 // The plan (intervals, near bands, path decision); needs finalize to have run.
 hipError_t launch_ff_plan(const Work& w, const FarField& f, hipStream_t s);

@@ -228,16 +228,20 @@ template <int K, int CB>
 __global__ __launch_bounds__(256) void wbuild_kernel(Work w) {
   wbuild_body<K, CB>(w, blockIdx.x, blockIdx.y);
 }
-// Far-field product: only the blocks of W it reads (the near band and the extra
-// near pairs of each column block), all of W when its plan fell back to the
-// dense product.  Row tiles of 256 coincide with its row blocks.
+// Far-field product: only the rows of W it reads (the near band and the further
+// near ranges of each column block, at the 256-row granularity of this kernel),
+// all of W when its plan fell back to the dense product.
 template <int K, int CB>
 __global__ __launch_bounds__(256) void wbuild_ff_kernel(Work w, FarField f) {
   if (__builtin_nontemporal_load(&f.flags[0]) == 0) {
-    const int nb = f.nb;
-    const int J = min((int)blockIdx.x, nb - 1), I = min((int)blockIdx.y * CB / 256, nb - 1);
-    bool need = J >= f.near[2 * I] && J <= f.near[2 * I + 1];
-    for (int r = 0; r < GSEG - 2; ++r) need = need || f.extra[I * (GSEG - 2) + r] == J;
+    const int I = min((int)blockIdx.y * CB / 256, f.nb - 1);
+    const int t0 = blockIdx.x * 256, t1 = min(w.n, t0 + 256);  // rows of this tile
+    auto hits = [&](int hlo, int hhi) {
+      return hlo >= 0 && ff_row_begin(f, hlo) < t1 && ff_row_end(f, hhi) > t0;
+    };
+    bool need = hits(f.near[2 * I], f.near[2 * I + 1]);
+    for (int r = 0; r < GSEG - 2; ++r)
+      need = need || hits(f.extra[2 * (I * (GSEG - 2) + r)], f.extra[2 * (I * (GSEG - 2) + r) + 1]);
     if (!need) return;
   }
   wbuild_body<K, CB>(w, blockIdx.x, blockIdx.y);
