@@ -236,10 +236,12 @@ __global__ __launch_bounds__(256) void ff_interval_kernel(Work w, FarField f) {
 }
 
 // Column block I and row block h far apart: distance at least etac times the
-// column width and etar times the row width (false if any bound is NaN).
-__device__ __forceinline__ bool ff_far(const FarField& f, int I, int h) {
-  const double ylo = f.ivr[2 * h], yhi = f.ivr[2 * h + 1];
-  const double xlo = f.ivc[2 * I], xhi = f.ivc[2 * I + 1];
+// column width and etar times the row width (false if any bound is NaN); ivr and
+// ivc are the plan's copies of the intervals.
+__device__ __forceinline__ bool ff_far(const FarField& f, const double* ivr, const double* ivc,
+                                       int I, int h) {
+  const double ylo = ivr[2 * h], yhi = ivr[2 * h + 1];
+  const double xlo = ivc[2 * I], xhi = ivc[2 * I + 1];
   const double dist = fmax(xlo - yhi, ylo - xhi);
   return dist >= f.etac * (xhi - xlo) && dist >= f.etar * (yhi - ylo);
 }
@@ -268,6 +270,8 @@ __global__ __launch_bounds__(256) void ff_plan_kernel(Work w, FarField f) {
   __shared__ int s_ok, s_full;
   __shared__ int s_sl[FF_MAXNB];     // k-slices of each column block's product
   __shared__ short s_inv[FF_MAXNB];  // column block of each launch position
+  // the intervals, read many times by the near-row searches
+  __shared__ double s_ivr[2 * (2 * FF_MAXNB + 1)], s_ivc[2 * FF_MAXNB];  // nr <= 2 nb + 1
   __shared__ double s_cr[FF_PMAX], s_cc[FF_PMAX];
   const int n = w.n, k = w.k, nb = f.nb, nr = f.nr;
   const int kpr = k * f.pr, kpc = k * f.pc, rpc = FF_B / f.rb;
@@ -277,13 +281,15 @@ __global__ __launch_bounds__(256) void ff_plan_kernel(Work w, FarField f) {
   }
   if (threadIdx.x < f.pr) s_cr[threadIdx.x] = ff_cos(threadIdx.x, f.pr);
   if (threadIdx.x < f.pc) s_cc[threadIdx.x] = ff_cos(threadIdx.x, f.pc);
+  for (int e = threadIdx.x; e < 2 * nr; e += 256) s_ivr[e] = f.ivr[e];
+  for (int e = threadIdx.x; e < 2 * nb; e += 256) s_ivc[e] = f.ivc[e];
   __syncthreads();
   for (int h = threadIdx.x; h < nr; h += 256) {
-    const double lo = f.ivr[2 * h], hi = f.ivr[2 * h + 1];
+    const double lo = s_ivr[2 * h], hi = s_ivr[2 * h + 1];
     if (!(hi > lo && isfinite(lo) && isfinite(hi))) s_ok = 0;
   }
   for (int I = threadIdx.x; I < nb; I += 256) {
-    const double lo = f.ivc[2 * I], hi = f.ivc[2 * I + 1];
+    const double lo = s_ivc[2 * I], hi = s_ivc[2 * I + 1];
     if (!(hi > lo && isfinite(lo) && isfinite(hi))) s_ok = 0;
   }
   __syncthreads();
@@ -294,11 +300,11 @@ __global__ __launch_bounds__(256) void ff_plan_kernel(Work w, FarField f) {
     int hi = (I + 1 == nb) ? nr - 1 : min(nr - 1, (I + 1) * rpc);
     int cnt = 0;
     if (s_ok) {
-      while (lo > 0 && !ff_far(f, I, lo - 1)) --lo;
-      while (hi < nr - 1 && !ff_far(f, I, hi + 1)) ++hi;
+      while (lo > 0 && !ff_far(f, s_ivr, s_ivc, I, lo - 1)) --lo;
+      while (hi < nr - 1 && !ff_far(f, s_ivr, s_ivc, I, hi + 1)) ++hi;
       int run = -1;  // first row block of the current range of near blocks
       for (int h = 0; h <= nr; ++h) {
-        const bool nh = h < nr && (h < lo || h > hi) && !ff_far(f, I, h);
+        const bool nh = h < nr && (h < lo || h > hi) && !ff_far(f, s_ivr, s_ivc, I, h);
         if (nh && run < 0) run = h;
         if (!nh && run >= 0) {
           if (cnt < FF_XR) {
@@ -335,11 +341,11 @@ __global__ __launch_bounds__(256) void ff_plan_kernel(Work w, FarField f) {
   const bool ok = s_ok != 0;
   for (int e = threadIdx.x; e < nr * f.pr; e += 256) {
     const int h = e / f.pr;
-    f.yn[e] = ok ? ff_node(f.ivr[2 * h], f.ivr[2 * h + 1], s_cr[e % f.pr]) : 0.0;
+    f.yn[e] = ok ? ff_node(s_ivr[2 * h], s_ivr[2 * h + 1], s_cr[e % f.pr]) : 0.0;
   }
   for (int e = threadIdx.x; e < nb * f.pc; e += 256) {
     const int I = e / f.pc;
-    f.xn[e] = ok ? ff_node(f.ivc[2 * I], f.ivc[2 * I + 1], s_cc[e % f.pc]) : 0.0;
+    f.xn[e] = ok ? ff_node(s_ivc[2 * I], s_ivc[2 * I + 1], s_cc[e % f.pc]) : 0.0;
   }
   // P2M: M_h = Q(:, h) B_h
   for (int h = threadIdx.x; h < nr; h += 256) {
