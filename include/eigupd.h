@@ -138,18 +138,21 @@ enum {
                                   which); ignored for k != 2 */
   EIG_QW_FARFIELD = 1 << 9  /* FP64, n >= 2048: form Q' = Q W with the far blocks
                                of W (Sec. 2.4, eq. (10)) replaced by Chebyshev
-                               expansions of 1/(x - y) (blocks of 256 rows and
-                               columns, 24 nodes per interval): a band of exact
-                               block products plus three small products, about
-                               8x fewer flops at n = 8192.  A row block and a
-                               column block count as far when their distance is
-                               at least half the larger width; there the
-                               interpolant of 1/(x - y) errs by at most about
-                               1e-13 relative (Bernstein parameter 2 + sqrt(3),
-                               24 nodes), and by about 2e-15 for blocks one
-                               width apart.  The far entries of W are small
-                               next to the near ones, so Q' agrees with the
-                               dense product to about 1e-15 in practice.
+                               expansions of 1/(x - y) (column blocks of 256;
+                               row blocks of 128 up to k = 2, of 256 above): a
+                               band of exact block products plus three small
+                               products, about 9.5x fewer flops at n = 8192,
+                               k = 2.  A row block and a column block count as
+                               far when their distance is at least etac times
+                               the column block's width and etar times the row
+                               block's; there the interpolant of 1/(x - y)
+                               errs by at most about 3e-13 relative up to
+                               k = 2 (etac 0.45 with 24 nodes, etar 0.675 with
+                               22) and 1e-13 above (0.5 of either width, 24
+                               nodes), and by about 2e-15 for blocks one width
+                               apart.  The far entries of W are small next to
+                               the near ones, so Q' agrees with the dense
+                               product to about 1e-15 in practice.
                                Falls back to the dense
                                product on the device when the update merged
                                equal poles; ignored for n < 2048, for
@@ -158,7 +161,9 @@ enum {
                                (eig_update_batch).  Only the blocks of W
                                it reads are formed (the debug copy of W is then
                                partial).  Allocates its buffers (about
-                               2 k n^2 P / 256 doubles) on first use. */
+                               2 k n^2 24 / 256 doubles from k = 3, about
+                               k n^2 (22 / 128 + 24 / 256) up to k = 2) on
+                               first use. */
 };
 
 /* Ranks: the kernels are specialised for 1 <= k <= EIG_KMAX.  eig_update_rankk
@@ -416,8 +421,8 @@ int eig_batch_destroy(eig_batch_t b);
  *
  * Products: batches run with EIG_QW_FARFIELD, so matrices with n >= 2048 form
  * Q' by the far-field product; its buffers (about 2 EIG_KMAX n^2 24 / 256
- * doubles per such matrix) are allocated outside the arena on the matrix's
- * first update and kept.
+ * doubles per such matrix, the most over every rank) are allocated outside the
+ * arena on the matrix's first update and kept.
  *
  * Memory: one device arena of arena_bytes holds every n x n buffer.  A
  * resident matrix keeps its current Q there (8 n^2 bytes; lambda and O(n k)
