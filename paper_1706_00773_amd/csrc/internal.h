@@ -232,10 +232,12 @@ __host__ __device__ inline int ff_row_end(const FarField& f, int h) {
 }
 // Row block h is multiplied exactly for column block I (band or further range).
 __device__ inline bool ff_near(const FarField& f, int I, int h) {
-  bool nr = h >= f.near[2 * I] && h <= f.near[2 * I + 1];
-  for (int r = 0; r < GSEG - 2; ++r)
-    nr = nr || (h >= f.extra[2 * (I * (GSEG - 2) + r)] && h <= f.extra[2 * (I * (GSEG - 2) + r) + 1]);
-  return nr;
+  bool hit = h >= f.near[2 * I] && h <= f.near[2 * I + 1];
+  for (int r = 0; r < GSEG - 2; ++r) {
+    const int lo = f.extra[2 * (I * (GSEG - 2) + r)], hi = f.extra[2 * (I * (GSEG - 2) + r) + 1];
+    hit = hit || (h >= lo && h <= hi);
+  }
+  return hit;
 }
 bool ff_eligible(int n, int k);
 int ff_blocks(int n);
