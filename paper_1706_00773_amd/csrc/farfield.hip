@@ -37,9 +37,10 @@
 //
 // The plan (intervals, near rows, descriptors) is made on the device, so the
 // host does not wait.  When the update has merged equal-pole groups (W rows mixed
-// by reflectors), a degenerate interval, half or more of the column blocks over
-// all rows, or an error, the plan switches the product back to the dense kernel:
-// of the two paths launched, each exits at once unless it was chosen.
+// by reflectors), a degenerate interval, half or more of the column blocks with
+// half the rows or more exact, or an error, the plan switches the product back
+// to the dense kernel: of the two paths launched, each exits at once unless it
+// was chosen.
 #include "common.h"
 
 namespace eigupd {
@@ -320,7 +321,6 @@ __global__ __launch_bounds__(256) void ff_plan_kernel(Work w, FarField f) {
       cnt = 0;
       lo = 0;
       hi = nr - 1;
-      atomicAdd(&s_full, 1);
     }
     f.near[2 * I] = lo;
     f.near[2 * I + 1] = hi;
@@ -328,14 +328,20 @@ __global__ __launch_bounds__(256) void ff_plan_kernel(Work w, FarField f) {
       f.extra[2 * (I * FF_XR + r)] = -1;
       f.extra[2 * (I * FF_XR + r) + 1] = -2;
     }
-    int sl = (ff_row_end(f, hi) - ff_row_begin(f, lo) + 15) / 16 + (kpc + 15) / 16;
-    for (int r = 0; r < cnt; ++r)
-      sl += (ff_row_end(f, f.extra[2 * (I * FF_XR + r) + 1]) -
-             ff_row_begin(f, f.extra[2 * (I * FF_XR + r)]) + 15) / 16;
+    int rows = ff_row_end(f, hi) - ff_row_begin(f, lo);
+    int sl = (rows + 15) / 16 + (kpc + 15) / 16;
+    for (int r = 0; r < cnt; ++r) {
+      const int m = ff_row_end(f, f.extra[2 * (I * FF_XR + r) + 1]) -
+                    ff_row_begin(f, f.extra[2 * (I * FF_XR + r)]);
+      rows += m;
+      sl += (m + 15) / 16;
+    }
     s_sl[I] = sl;
+    if (2 * rows >= n) atomicAdd(&s_full, 1);  // half the rows or more exact
   }
   __syncthreads();
-  // half or more of the column blocks over all rows: the dense product is cheaper
+  // half or more of the column blocks take half the rows or more exactly: the
+  // dense product is cheaper
   if (threadIdx.x == 0 && 2 * s_full >= nb) s_ok = 0;
   __syncthreads();
   const bool ok = s_ok != 0;

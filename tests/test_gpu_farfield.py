@@ -62,6 +62,18 @@ def _check_oracle(u, lo, Qo):
     assert np.abs(Qo.T @ Qo - np.eye(n)).max() <= ORTH_TOL
 
 
+def _outlying_poles(n, t, seed):
+    """t poles uniform in [-1.4, -1.05] and t in [1.05, 1.4] around a bulk uniform in
+    [-1, 1] (the spectrum's ends after a chain of rank-2 updates), Haar Q, rank-2 K
+    of norm about 0.3."""
+    rng = np.random.default_rng(seed)
+    lo, hi = np.sort(rng.uniform(-1.4, -1.05, t)), np.sort(rng.uniform(1.05, 1.4, t))
+    lam = np.concatenate([lo, wl.distinct_uniform(n - 2 * t, -1.0, 1.0, 1e-6, rng), hi])
+    Q = wl.orthogonal_from(wl.gaussian_square(n, rng))
+    K = np.asfortranarray(0.3 * rng.standard_normal((n, 2)) / np.sqrt(n))
+    return wl.Update(lam, Q, K, wl.random_signs(2, rng), f"outlying-poles-n{n}")
+
+
 CASES = [
     ("rank2 e_j a^T + a e_j^T, n=2048", lambda: wl.plain_rank2(2048, seed=31, min_gap=1e-12)),
     ("ragged n=2500 (last block 452), k=3", lambda: wl.random_small(2500, 3, seed=32)),
@@ -71,9 +83,8 @@ CASES = [
     ("k=8, n=2048", lambda: wl.general_rankk(8, n=2048, seed=35)),
     ("clusters and tiny rows, n=4096", lambda: wl.clustered_rank2(4096, seed=36)),
     # the top root lies far above the spectrum: the last column block is close to
-    # six row blocks beyond its band, so it is multiplied over all rows and its
-    # product is launched first (the ragged and clusters cases move blocks with
-    # one extra pair ahead of the others)
+    # every row block, so its band widens over all rows and its product is
+    # launched first
     ("strong perturbation (||K|| ~ 10: outlying eigenvalues), n=2048",
      lambda: wl.random_small(2048, 2, seed=38, knorm=10.0)),
 ]
@@ -86,6 +97,38 @@ def test_farfield_matches_dense_and_oracle(name, make):
     ld, Qd, lf, Qf, info = _both(u)
     assert np.array_equal(ld, lf)
     # the far-field path ran (its fallback, the dense product, is bitwise Qd)
+    assert not np.array_equal(Qf, Qd)
+    assert np.abs(Qf - Qd).max() <= DIFF_TOL
+    _check_oracle(u, lf, Qf)
+
+
+def _further_ranges(lam, x, k):
+    """Ranges of near row blocks apart from each column block's band, from the
+    plan's rules (a band is the run of near row blocks around its column block)."""
+    pairs, _, _ = _far_pairs(lam, x, k)
+    rb = _rules(k)[0]
+    n = lam.size
+    nb, nr = n // 256, n // rb
+    far = {(I, h) for I, h, _, _ in pairs}
+    out = []
+    for I in range(nb):
+        near = [h for h in range(nr) if (I, h) not in far]
+        out.append(sum(1 for a, b in zip(near, near[1:]) if b != a + 1))
+    return out
+
+
+def test_outlying_poles_give_further_near_ranges():
+    """Poles spread beyond both ends of the bulk (the spectrum's ends after a chain
+    of rank-2 updates) widen the end row blocks, and column blocks two blocks in
+    multiply them exactly as ranges apart from their bands: the product's extra
+    segments."""
+    print("case farfield outlying poles at both ends, n=4096", flush=True)
+    u = _outlying_poles(4096, 30, seed=39)
+    ld, Qd, lf, Qf, info = _both(u)
+    assert np.array_equal(ld, lf)
+    ranges = _further_ranges(np.asarray(u.lam), lf, 2)
+    print(f"  further near ranges per column block: {ranges}", flush=True)
+    assert sum(ranges) >= 2 and max(ranges) <= 4
     assert not np.array_equal(Qf, Qd)
     assert np.abs(Qf - Qd).max() <= DIFF_TOL
     _check_oracle(u, lf, Qf)
