@@ -141,14 +141,14 @@ enum {
                                expansions of 1/(x - y) (column blocks of 256;
                                row blocks of 128 up to k = 2, of 256 above): a
                                band of exact block products plus three small
-                               products, about 9.5x fewer flops at n = 8192,
+                               products, about 9.8x fewer flops at n = 8192,
                                k = 2.  A row block and a column block count as
                                far when their distance is at least etac times
                                the column block's width and etar times the row
                                block's; there the interpolant of 1/(x - y)
                                errs by at most about 3e-13 relative up to
-                               k = 2 (etac 0.45 with 24 nodes, etar 0.675 with
-                               22) and 1e-13 above (0.5 of either width, 24
+                               k = 2 (etac 0.45 with 24 nodes, etar 0.85 with
+                               20) and 1e-13 above (0.5 of either width, 24
                                nodes), and by about 2e-15 for blocks one width
                                apart.  The far entries of W are small next to
                                the near ones, so Q' agrees with the dense
@@ -162,7 +162,7 @@ enum {
                                it reads are formed (the debug copy of W is then
                                partial).  Allocates its buffers (about
                                2 k n^2 24 / 256 doubles from k = 3, about
-                               k n^2 (22 / 128 + 24 / 256) up to k = 2) on
+                               k n^2 (20 / 128 + 24 / 256) up to k = 2) on
                                first use. */
 };
 

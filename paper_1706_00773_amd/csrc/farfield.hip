@@ -63,10 +63,11 @@ constexpr int FF_XR = GSEG - 2;  // further near ranges per column block
 //  - Up to rank 2: rb = FF_B / 2.  The row blocks next to the band lie about
 //    half a column width away (one row block between).  Columns: etac = 0.45,
 //    pc = 24 (rho = 3.52, about 3e-13 relative at the limit, 7.5e-14 at half a
-//    width); rows: etar = 0.675, pr = 22 (rho = 4.48, about 2e-14 at the limit;
+//    width); rows: etar = 0.85, pr = 20 (rho = 5.21, about 2e-14 at the limit;
 //    those row blocks are one row width away).  With uniform spectra about one
-//    in six of those row blocks falls inside etac (random spacing) and is
-//    multiplied exactly.  pc = 32 with etac = 0.35 (1e-15 at the limit) was
+//    in four of those row blocks falls inside a limit (random spacing) and is
+//    multiplied exactly.  pr = 22 with etar = 0.675 (the same error at its
+//    limit, fewer such blocks) took 0.025 ms more per n = 8192 update.  pc = 32 with etac = 0.35 (1e-15 at the limit) was
 //    measured at n = 8192: M2L's 1024 column tiles instead of 768 took 0.15 ms
 //    more per update, with the same residual and orthogonality against eigh.
 struct FfCfg {
@@ -74,7 +75,7 @@ struct FfCfg {
   double etar, etac;
 };
 __host__ __device__ static inline FfCfg ff_cfg(int k) {
-  return k <= 2 ? FfCfg{FF_B / 2, 22, 24, 0.675, 0.45} : FfCfg{FF_B, 24, 24, 0.5, 0.5};
+  return k <= 2 ? FfCfg{FF_B / 2, 20, 24, 0.85, 0.45} : FfCfg{FF_B, 24, 24, 0.5, 0.5};
 }
 
 int ff_blocks(int n) { return n / FF_B; }
@@ -489,8 +490,8 @@ hipError_t launch_qw_farfield(const Work& w, const FarField& f, hipStream_t s) {
   const long long ne = (long long)mr * mc;
   hipLaunchKernelGGL(ff_t_kernel, dim3((unsigned)((ne + 255) / 256)), dim3(256), 0, s, f);
   const dim3 wg((2 * n + 255) / 256);
-  if (f.pr == 22 && f.pc == 24)
-    hipLaunchKernelGGL((ff_weights_kernel<22, 24>), wg, dim3(256), 0, s, w, f);
+  if (f.pr == 20 && f.pc == 24)
+    hipLaunchKernelGGL((ff_weights_kernel<20, 24>), wg, dim3(256), 0, s, w, f);
   else if (f.pr == 24 && f.pc == 24)
     hipLaunchKernelGGL((ff_weights_kernel<24, 24>), wg, dim3(256), 0, s, w, f);
   else

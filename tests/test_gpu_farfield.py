@@ -282,7 +282,7 @@ def test_full_size_n8192(name, make):
 
 def _rules(k):
     """Rows per row block and the row / column separation factors of the plan."""
-    return (128, 0.675, 0.45) if k <= 2 else (256, 0.5, 0.5)
+    return (128, 0.85, 0.45) if k <= 2 else (256, 0.5, 0.5)
 
 
 def _far_pairs(lam, x, k):
@@ -362,7 +362,7 @@ def _far_errors(lam, ld, K, Wd, Wf, pairs, rows, cols):
 
 def _limit_spectrum_rank2(margin, rng):
     """16 row blocks of 128 poles in periods of four (a, b, c, d): a, b and c 0.3
-    wide, d one unit wide.  d starts 0.675 (1 + margin) after b, so column block
+    wide, d one unit wide.  d starts 0.85 (1 + margin) after b, so column block
     (a, b) and row block d are just far on the row side.  The next period's b
     starts 0.45 (1 + margin) widths of column block (c, d) after d, so that pair
     is just far on the column side.  Blocks whose column points end a block are
@@ -385,18 +385,18 @@ def _limit_spectrum_rank2(margin, rng):
             b_end = put(d_end + 0.45 * (d_end - c_lo) * (1.0 + margin), 0.3)
         c_lo = b_end + 0.1
         put(c_lo, 0.3)
-        d_end = put(b_end + 0.675 * (1.0 + margin), 1.0)
+        d_end = put(b_end + 0.85 * (1.0 + margin), 1.0)
     return np.concatenate(halves)
 
 
 def test_far_pairs_at_the_acceptance_limits_up_to_rank_2():
     """Up to rank 2 the row blocks hold 128 poles; a pair is far when its distance
-    is at least 0.45 of the column block's width and 0.675 of the row block's.
+    is at least 0.45 of the column block's width and 0.85 of the row block's.
     Pairs placed at (1 + 2e-4) times either limit: with Q = I and k = 1, Q' is W
     itself, W(j, p) = u_j c_p / (x_p - lambda_j) with no cancellation, so the
     far-field result against the dense one measures the error of the Chebyshev
     expansion entry by entry: about 3e-13 at the column-side limit (24 nodes,
-    rho = 3.52), 2e-14 at the row-side one (22 nodes, rho = 4.48)."""
+    rho = 3.52), 2e-14 at the row-side one (20 nodes, rho = 5.21)."""
     rng = np.random.default_rng(2026)
     lam = _limit_spectrum_rank2(2e-4, rng)
     n = lam.size
