@@ -589,7 +589,7 @@ FF_B = 256  # columns per column block of the far-field product
 def farfield_cfg(k):
     """Rows per row block and nodes per row / column interval of the far-field plan
     (half-width row blocks up to rank 2)."""
-    return (128, 20, 24) if k <= 2 else (256, 24, 24)
+    return (128, 20, 24) if k <= 2 else (256, 20, 20)
 
 
 def farfield_flops(n, k):

@@ -148,9 +148,9 @@ enum {
                                block's; there the interpolant of 1/(x - y)
                                errs by at most about 3e-13 relative up to
                                k = 2 (etac 0.45 with 24 nodes, etar 0.85 with
-                               20) and 1e-13 above (0.5 of either width, 24
-                               nodes), and by about 2e-15 for blocks one width
-                               apart.  The far entries of W are small next to
+                               20) and about 6e-14 above (0.78 of either width,
+                               20 nodes), and by about 2e-15 for blocks one
+                               width apart.  The far entries of W are small next to
                                the near ones, so Q' agrees with the dense
                                product to about 1e-15 in practice.
                                Falls back to the dense
@@ -161,7 +161,7 @@ enum {
                                (eig_update_batch).  Only the blocks of W
                                it reads are formed (the debug copy of W is then
                                partial).  Allocates its buffers (about
-                               2 k n^2 24 / 256 doubles from k = 3, about
+                               2 k n^2 20 / 256 doubles from k = 3, about
                                k n^2 (20 / 128 + 24 / 256) up to k = 2) on
                                first use. */
 };
@@ -420,7 +420,7 @@ int eig_batch_destroy(eig_batch_t b);
  * predecessors were meant to produce.
  *
  * Products: batches run with EIG_QW_FARFIELD, so matrices with n >= 2048 form
- * Q' by the far-field product; its buffers (about 2 EIG_KMAX n^2 24 / 256
+ * Q' by the far-field product; its buffers (about 2 EIG_KMAX n^2 20 / 256
  * doubles per such matrix, the most over every rank) are allocated outside the
  * arena on the matrix's first update and kept.
  *

@@ -57,9 +57,11 @@ constexpr int FF_XR = GSEG - 2;  // further near ranges per column block
 // 1/(x - y) in x over a column interval of width w, with the singularity at
 // distance d, errs by about 4 rho^(-pc), rho = s + sqrt(s^2 - 1), s = 1 + 2 d / w
 // (the factor 4 measured); the same holds in y with pr and the row width.
-//  - Ranks above 2: rb = FF_B, pr = pc = 24, far when d >= 0.5 of both widths:
-//    rho = 2 + sqrt(3) at the limit, 7.5e-14 measured there; blocks one width
-//    apart, which is what uniform spectra give, are at the rounding level.
+//  - Ranks above 2: rb = FF_B, pr = pc = 20, far when d >= 0.78 of both widths:
+//    rho = 4.92 at the limit, about 6e-14; blocks one width apart, which is what
+//    uniform spectra give, are at the rounding level.  24 nodes with a factor of
+//    0.5 (7.5e-14 at its limit) made M2L 44% larger: n = 8192 updates at rank 4
+//    and 8 ran at 232 and 127 updates/s against 243 and 134.
 //  - Up to rank 2: rb = FF_B / 2.  The row blocks next to the band lie about
 //    half a column width away (one row block between).  Columns: etac = 0.45,
 //    pc = 24 (rho = 3.52, about 3e-13 relative at the limit, 7.5e-14 at half a
@@ -75,7 +77,7 @@ struct FfCfg {
   double etar, etac;
 };
 __host__ __device__ static inline FfCfg ff_cfg(int k) {
-  return k <= 2 ? FfCfg{FF_B / 2, 20, 24, 0.85, 0.45} : FfCfg{FF_B, 24, 24, 0.5, 0.5};
+  return k <= 2 ? FfCfg{FF_B / 2, 20, 24, 0.85, 0.45} : FfCfg{FF_B, 20, 20, 0.78, 0.78};
 }
 
 int ff_blocks(int n) { return n / FF_B; }
@@ -492,8 +494,8 @@ hipError_t launch_qw_farfield(const Work& w, const FarField& f, hipStream_t s) {
   const dim3 wg((2 * n + 255) / 256);
   if (f.pr == 20 && f.pc == 24)
     hipLaunchKernelGGL((ff_weights_kernel<20, 24>), wg, dim3(256), 0, s, w, f);
-  else if (f.pr == 24 && f.pc == 24)
-    hipLaunchKernelGGL((ff_weights_kernel<24, 24>), wg, dim3(256), 0, s, w, f);
+  else if (f.pr == 20 && f.pc == 20)
+    hipLaunchKernelGGL((ff_weights_kernel<20, 20>), wg, dim3(256), 0, s, w, f);
   else
     return hipErrorInvalidValue;
   hipError_t e = hipGetLastError();

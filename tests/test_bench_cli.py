@@ -38,9 +38,9 @@ def test_farfield_flops_closed_form():
     band = 2.0 * n * (256 * 384 + 7 * 256 * 512 + 452 * 580)
     assert bench.farfield_flops(n, 1) == (band + 2.0 * n * n * 20 + 2.0 * n * n * 24
                                           + 2.0 * n * (19 * 20) * (9 * 24))
-    # ranks above 2 keep row blocks of 256 with 24 nodes: three row blocks per
-    # column block (two at the ends)
-    p = 24
+    # ranks above 2 take row blocks of 256 with 20 nodes on either side: three
+    # row blocks per column block (two at the ends)
+    p = 20
     sizes = [256] * 8 + [452]
     band = sum(2.0 * n * sizes[i] * sum(sizes[max(0, i - 1):i + 2]) for i in range(9))
     assert bench.farfield_flops(n, 3) == band + 2 * (2.0 * n * n * 3 * p) + 2.0 * 3 * n * (9 * p) ** 2
