@@ -280,6 +280,49 @@ def test_full_size_n8192(name, make):
     assert np.abs(G).max() <= ORTH_TOL
 
 
+def test_full_size_n16384_rank2():
+    """n = 16384, k = 2 (the benchmark's rank-2 workload at twice the order): 128
+    row blocks of 128 and 64 column blocks, the largest interaction product the
+    tests run.  Q' entrywise against the dense product, eigenvalues bitwise equal,
+    residual against A' and orthogonality on 128 sampled columns (on the GPU)."""
+    import torch
+
+    print("case farfield rank-2 e_j a^T + a e_j^T, n=16384", flush=True)
+    n, dev = 16384, "cuda:0"
+    u = wl.plain_rank2(n, seed=1006, device=dev, min_gap=1e-12)
+    K = colmajor(np.asarray(u.K), dev)
+    lam = torch.as_tensor(np.asarray(u.lam), device=dev)
+    outs = []
+    for mode in (0, FF):
+        with eu.EigState(n, 0) as s:
+            s.upload(lam, u.Q)
+            s.update(K, u.sigma, mode)
+            lo = torch.empty(n, dtype=torch.float64, device=dev)
+            Qo = torch.empty((n, n), dtype=torch.float64, device=dev).t()
+            s.query(lo, Qo)
+            outs.append((lo, Qo))
+    (ld, Qd), (lf, Qf) = outs
+    assert torch.equal(ld, lf)
+    assert not torch.equal(Qf, Qd)  # the far-field path ran
+    diff = float((Qf - Qd).abs().max())
+    del Qd
+    cols = torch.as_tensor(np.sort(np.random.default_rng(46).choice(n, 128, replace=False)),
+                           device=dev)
+    Qs = Qf[:, cols].contiguous()
+    sig = torch.as_tensor(np.asarray(u.sigma, dtype=np.float64), device=dev)
+    Aq = u.Q @ (lam[:, None] * (u.Q.t().contiguous() @ Qs)) + K @ (sig[:, None] * (K.t() @ Qs))
+    scale = float(lf.abs().max())
+    res = float((Aq - Qs * lf[cols][None, :]).abs().max()) / scale
+    G = Qf.t().contiguous() @ Qs
+    G[cols, torch.arange(cols.numel(), device=dev)] -= 1.0
+    orth = float(G.abs().max())
+    print(f"  max |Q'_far - Q'_dense| {diff:.2e}, residual {res:.2e}, orthogonality {orth:.2e}",
+          flush=True)
+    assert diff <= DIFF_TOL
+    assert res <= RES_TOL
+    assert orth <= ORTH_TOL
+
+
 def _rules(k):
     """Rows per row block and the row / column separation factors of the plan."""
     return (128, 0.85, 0.45) if k <= 2 else (256, 0.78, 0.78)
