@@ -280,16 +280,21 @@ def test_full_size_n8192(name, make):
     assert np.abs(G).max() <= ORTH_TOL
 
 
-def test_full_size_n16384_rank2():
-    """n = 16384, k = 2 (the benchmark's rank-2 workload at twice the order): 128
-    row blocks of 128 and 64 column blocks, the largest interaction product the
-    tests run.  Q' entrywise against the dense product, eigenvalues bitwise equal,
+@pytest.mark.parametrize("k", [2, 4])
+def test_full_size_n16384(k):
+    """n = 16384: at k = 2 the benchmark's rank-2 workload at twice the order (128
+    row blocks of 128, 64 column blocks: the largest interaction product the tests
+    run), at k = 4 the general rank-k workload (row blocks of 256, 20 nodes each
+    side).  Q' entrywise against the dense product, eigenvalues bitwise equal,
     residual against A' and orthogonality on 128 sampled columns (on the GPU)."""
     import torch
 
-    print("case farfield rank-2 e_j a^T + a e_j^T, n=16384", flush=True)
+    print(f"case farfield rank {k}, n=16384", flush=True)
     n, dev = 16384, "cuda:0"
-    u = wl.plain_rank2(n, seed=1006, device=dev, min_gap=1e-12)
+    if k == 2:
+        u = wl.plain_rank2(n, seed=1006, device=dev, min_gap=1e-12)
+    else:
+        u = wl.general_rankk(k, n=n, seed=1007, device=dev)
     K = colmajor(np.asarray(u.K), dev)
     lam = torch.as_tensor(np.asarray(u.lam), device=dev)
     outs = []
