@@ -7,6 +7,7 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <algorithm>
 #include <new>
 #include <vector>
 
@@ -420,7 +421,10 @@ int eig_update_rankk(eig_state_t s, int64_t k, const double* K, int64_t ldk, con
   const bool farfield = (mode & EIG_QW_FARFIELD) && prec == EIG_GEMM_FP64 && any_product &&
                         ff_eligible((int)n, part_k);
   if (farfield) {
-    const int rc = grow(&s->ff_block, &s->ff_bytes, ff_bytes((int)n, part_k));
+    // the parts' ranks differ by at most one; the buffers depend on the rank
+    // through the row-block size too, so take the larger need of the two
+    const size_t ffb = std::max(ff_bytes((int)n, part_k), ff_bytes((int)n, (int)(k / parts)));
+    const int rc = grow(&s->ff_block, &s->ff_bytes, ffb);
     if (rc != EIG_OK) return rc;
   }
   if (parts > 1 && !s->Q_x) {
