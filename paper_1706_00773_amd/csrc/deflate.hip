@@ -174,9 +174,13 @@ __device__ __forceinline__ void deflate_body(const Work& w) {
   }
   const int n_groups = carry;
   __syncthreads();
+  // Every group a single row (the usual case): no group records, reflectors or
+  // QR are needed, and each kept row starts its own segment (phase 4's short
+  // form below gives the same arrays as the general one).
+  const bool singles = (n_groups == n_nt);
   double spread = 0.0;
   carry = 0;
-  for (int base = 0; base < n_groups; base += DNT) {
+  for (int base = 0; !singles && base < n_groups; base += DNT) {
     const int g = base + tid;
     int multi = 0;
     if (g < n_groups) {
@@ -203,7 +207,36 @@ __device__ __forceinline__ void deflate_body(const Work& w) {
 
   // 4. reduced problem, segments and deflated list, in row order
   int ck = 0, cd = 0, cs = 0;
-  for (int base = 0; base < n; base += DNT) {
+  for (int base = 0; singles && base < n; base += DNT) {
+    // rows kept exactly when not tiny; one scan gives the reduced row, the
+    // segment (the same index) and, by difference, the deflated position
+    const int j = base + tid;
+    const int kept = (j < n && w.rmap[j] >= 0) ? 1 : 0;
+    int tk;
+    const int ek = block_excl_scan<DNT>(kept, shi, &tk);
+    if (j < n) {
+      if (kept) {
+        const int ri = ck + ek;
+        w.rd[ri] = lam[j];
+#pragma unroll
+        for (int c = 0; c < K; ++c) w.ru[(size_t)ri * K + c] = w.U[(size_t)j * K + c];
+        w.rrow[ri] = j;
+        w.row_seg[ri] = cs + ek;
+        w.seg_start[cs + ek] = ri;
+        w.seg_r[cs + ek] = 1;
+        w.rmap[j] = ri;
+      } else {
+        const int di = cd + tid - ek;
+        w.dval[di] = lam[j];
+        w.drow[di] = j;
+        w.rmap[j] = -1;
+      }
+    }
+    ck += tk;
+    cs += tk;
+    cd += min(DNT, n - base) - tk;
+  }
+  for (int base = 0; !singles && base < n; base += DNT) {
     const int j = base + tid;
     int kept = 0, defl = 0, segst = 0;
     int t = -1, g = -1, m = 1, pos = 0;
