@@ -87,7 +87,7 @@ __device__ __forceinline__ void deflate_body(const Work& w) {
   constexpr int DNT = dnt<K>();
   __shared__ double shd[DNT / 64 + 1];
   __shared__ int shi[DNT / 64 + 1];
-  __shared__ int s_bad;
+  __shared__ int s_bad, s_odd;
   if (update_cancelled(w.st)) return;
   const int n = w.n, tid = threadIdx.x;
   const double* __restrict__ lam = w.lam_in;
@@ -130,157 +130,186 @@ __device__ __forceinline__ void deflate_body(const Work& w) {
   const double tol_abs = (sfro > 0.0) ? TAU_ROW * ahat / sfro : 0.0;  // on ||u_j||
   const double tol_gap = TAU_GAP * ahat;
 
-  // 2. tiny rows; compaction of the others (rmap temporarily holds the
-  //    non-tiny position of each row, or -1)
-  double tiny2 = 0.0;
-  int carry = 0;
-  for (int base = 0; base < n; base += DNT) {
-    const int j = base + tid;
-    int keep = 0;
-    if (j < n) {
-      double s = 0.0;
+  // The usual case: no tiny row and no two poles within tol_gap.  Every row is
+  // then kept as a segment of its own and the reduced problem is the input: one
+  // pass checks, one writes (the general phases below give the same arrays).
+  if (tid == 0) s_odd = 0;
+  __syncthreads();
+  int odd = 0;
+  for (int j = tid; j < n; j += DNT) {
+    double s = 0.0;
 #pragma unroll
-      for (int c = 0; c < K; ++c) s += w.U[(size_t)j * K + c] * w.U[(size_t)j * K + c];
-      const bool t = !(sqrt(s) > tol_abs);
-      w.tiny[j] = t ? 1 : 0;
-      keep = t ? 0 : 1;
-      if (t) tiny2 += s;
-    }
-    int tot;
-    const int ex = block_excl_scan<DNT>(keep, shi, &tot);
-    if (j < n) {
-      w.rmap[j] = keep ? carry + ex : -1;
-      if (keep) w.nt_list[carry + ex] = j;
-    }
-    carry += tot;
+    for (int c = 0; c < K; ++c) s += w.U[(size_t)j * K + c] * w.U[(size_t)j * K + c];
+    odd |= !(sqrt(s) > tol_abs);
+    odd |= (j > 0) && !(lam[j] - lam[j - 1] > tol_gap);
   }
-  const int n_nt = carry;
+  if (odd) atomicOr(&s_odd, 1);
   __syncthreads();
+  const bool plain = (s_odd == 0);
+  double tiny2 = 0.0, spread = 0.0, rem2 = 0.0;
+  int n_nt = n, n_mg = 0, ck = n, cd = 0, cs = n;
+  for (int j = tid; plain && j < n; j += DNT) {
+    w.rd[j] = lam[j];
+#pragma unroll
+    for (int c = 0; c < K; ++c) w.ru[(size_t)j * K + c] = w.U[(size_t)j * K + c];
+    w.rrow[j] = j;
+    w.row_seg[j] = j;
+    w.seg_start[j] = j;
+    w.seg_r[j] = 1;
+    w.rmap[j] = j;
+  }
+  if (!plain) {
+    // 2. tiny rows; compaction of the others (rmap temporarily holds the
+    //    non-tiny position of each row, or -1)
+    int carry = 0;
+    for (int base = 0; base < n; base += DNT) {
+      const int j = base + tid;
+      int keep = 0;
+      if (j < n) {
+        double s = 0.0;
+  #pragma unroll
+        for (int c = 0; c < K; ++c) s += w.U[(size_t)j * K + c] * w.U[(size_t)j * K + c];
+        const bool t = !(sqrt(s) > tol_abs);
+        w.tiny[j] = t ? 1 : 0;
+        keep = t ? 0 : 1;
+        if (t) tiny2 += s;
+      }
+      int tot;
+      const int ex = block_excl_scan<DNT>(keep, shi, &tot);
+      if (j < n) {
+        w.rmap[j] = keep ? carry + ex : -1;
+        if (keep) w.nt_list[carry + ex] = j;
+      }
+      carry += tot;
+    }
+    n_nt = carry;
+    __syncthreads();
 
-  // 3. groups of near-equal poles among the non-tiny rows
-  carry = 0;
-  for (int base = 0; base < n_nt; base += DNT) {
-    const int t = base + tid;
-    int start = 0;
-    if (t < n_nt) start = (t == 0) || (lam[w.nt_list[t]] - lam[w.nt_list[t - 1]] > tol_gap);
-    int tot;
-    const int ex = block_excl_scan<DNT>(start, shi, &tot);
-    if (t < n_nt) {
-      const int gid = carry + ex + start - 1;
-      w.grp_id[t] = gid;
-      if (start) w.g_first[gid] = t;
+    // 3. groups of near-equal poles among the non-tiny rows
+    carry = 0;
+    for (int base = 0; base < n_nt; base += DNT) {
+      const int t = base + tid;
+      int start = 0;
+      if (t < n_nt) start = (t == 0) || (lam[w.nt_list[t]] - lam[w.nt_list[t - 1]] > tol_gap);
+      int tot;
+      const int ex = block_excl_scan<DNT>(start, shi, &tot);
+      if (t < n_nt) {
+        const int gid = carry + ex + start - 1;
+        w.grp_id[t] = gid;
+        if (start) w.g_first[gid] = t;
+      }
+      carry += tot;
     }
-    carry += tot;
-  }
-  const int n_groups = carry;
-  __syncthreads();
-  // Every group a single row (the usual case): no group records, reflectors or
-  // QR are needed, and each kept row starts its own segment (phase 4's short
-  // form below gives the same arrays as the general one).
-  const bool singles = (n_groups == n_nt);
-  double spread = 0.0;
-  carry = 0;
-  for (int base = 0; !singles && base < n_groups; base += DNT) {
-    const int g = base + tid;
-    int multi = 0;
-    if (g < n_groups) {
-      const int f = w.g_first[g];
-      const int next = (g + 1 < n_groups) ? w.g_first[g + 1] : n_nt;
-      const int m = next - f;
-      w.g_m[g] = m;
-      w.g_val[g] = lam[w.nt_list[f]];
-      w.g_r[g] = 1;
-      w.g_h[g] = 0;
-      multi = (m >= 2);
-      if (multi) spread = fmax(spread, lam[w.nt_list[next - 1]] - lam[w.nt_list[f]]);
+    const int n_groups = carry;
+    __syncthreads();
+    // Every group a single row (the usual case): no group records, reflectors or
+    // QR are needed, and each kept row starts its own segment (phase 4's short
+    // form below gives the same arrays as the general one).
+    const bool singles = (n_groups == n_nt);
+    carry = 0;
+    for (int base = 0; !singles && base < n_groups; base += DNT) {
+      const int g = base + tid;
+      int multi = 0;
+      if (g < n_groups) {
+        const int f = w.g_first[g];
+        const int next = (g + 1 < n_groups) ? w.g_first[g + 1] : n_nt;
+        const int m = next - f;
+        w.g_m[g] = m;
+        w.g_val[g] = lam[w.nt_list[f]];
+        w.g_r[g] = 1;
+        w.g_h[g] = 0;
+        multi = (m >= 2);
+        if (multi) spread = fmax(spread, lam[w.nt_list[next - 1]] - lam[w.nt_list[f]]);
+      }
+      int tot;
+      const int ex = block_excl_scan<DNT>(multi, shi, &tot);
+      if (multi) w.mg_list[carry + ex] = g;
+      carry += tot;
     }
-    int tot;
-    const int ex = block_excl_scan<DNT>(multi, shi, &tot);
-    if (multi) w.mg_list[carry + ex] = g;
-    carry += tot;
-  }
-  const int n_mg = carry;
-  __syncthreads();
-  double rem2 = 0.0;
-  for (int idx = tid; idx < n_mg; idx += DNT) group_qr<K>(w, w.mg_list[idx], tol_abs, &rem2);
-  __syncthreads();
+    n_mg = carry;
+    __syncthreads();
+    for (int idx = tid; idx < n_mg; idx += DNT) group_qr<K>(w, w.mg_list[idx], tol_abs, &rem2);
+    __syncthreads();
 
-  // 4. reduced problem, segments and deflated list, in row order
-  int ck = 0, cd = 0, cs = 0;
-  for (int base = 0; singles && base < n; base += DNT) {
-    // rows kept exactly when not tiny; one scan gives the reduced row, the
-    // segment (the same index) and, by difference, the deflated position
-    const int j = base + tid;
-    const int kept = (j < n && w.rmap[j] >= 0) ? 1 : 0;
-    int tk;
-    const int ek = block_excl_scan<DNT>(kept, shi, &tk);
-    if (j < n) {
+    // 4. reduced problem, segments and deflated list, in row order
+    ck = 0;
+    cd = 0;
+    cs = 0;
+    for (int base = 0; singles && base < n; base += DNT) {
+      // rows kept exactly when not tiny; one scan gives the reduced row, the
+      // segment (the same index) and, by difference, the deflated position
+      const int j = base + tid;
+      const int kept = (j < n && w.rmap[j] >= 0) ? 1 : 0;
+      int tk;
+      const int ek = block_excl_scan<DNT>(kept, shi, &tk);
+      if (j < n) {
+        if (kept) {
+          const int ri = ck + ek;
+          w.rd[ri] = lam[j];
+  #pragma unroll
+          for (int c = 0; c < K; ++c) w.ru[(size_t)ri * K + c] = w.U[(size_t)j * K + c];
+          w.rrow[ri] = j;
+          w.row_seg[ri] = cs + ek;
+          w.seg_start[cs + ek] = ri;
+          w.seg_r[cs + ek] = 1;
+          w.rmap[j] = ri;
+        } else {
+          const int di = cd + tid - ek;
+          w.dval[di] = lam[j];
+          w.drow[di] = j;
+          w.rmap[j] = -1;
+        }
+      }
+      ck += tk;
+      cs += tk;
+      cd += min(DNT, n - base) - tk;
+    }
+    for (int base = 0; !singles && base < n; base += DNT) {
+      const int j = base + tid;
+      int kept = 0, defl = 0, segst = 0;
+      int t = -1, g = -1, m = 1, pos = 0;
+      if (j < n) {
+        t = w.rmap[j];
+        if (t < 0) {
+          defl = 1;
+        } else {
+          g = w.grp_id[t];
+          m = w.g_m[g];
+          pos = t - w.g_first[g];
+          kept = (m == 1) || (pos < w.g_r[g]);
+          defl = !kept;
+          segst = kept && (pos == 0);
+        }
+      }
+      int tk, td, ts;
+      const int ek = block_excl_scan<DNT>(kept, shi, &tk);
+      const int ed = block_excl_scan<DNT>(defl, shi, &td);
+      const int es = block_excl_scan<DNT>(segst, shi, &ts);
       if (kept) {
         const int ri = ck + ek;
-        w.rd[ri] = lam[j];
-#pragma unroll
-        for (int c = 0; c < K; ++c) w.ru[(size_t)ri * K + c] = w.U[(size_t)j * K + c];
+        const int sid = cs + es + segst - 1;
+        w.rd[ri] = (m == 1) ? lam[j] : w.g_val[g];
+  #pragma unroll
+        for (int c = 0; c < K; ++c)
+          w.ru[(size_t)ri * K + c] = (m == 1) ? w.U[(size_t)j * K + c] : w.urot[(size_t)t * K + c];
         w.rrow[ri] = j;
-        w.row_seg[ri] = cs + ek;
-        w.seg_start[cs + ek] = ri;
-        w.seg_r[cs + ek] = 1;
-        w.rmap[j] = ri;
-      } else {
-        const int di = cd + tid - ek;
+        w.row_seg[ri] = sid;
+        if (segst) {
+          w.seg_start[sid] = ri;
+          w.seg_r[sid] = (m == 1) ? 1 : w.g_r[g];
+        }
+      }
+      if (defl) {
+        const int di = cd + ed;
         w.dval[di] = lam[j];
         w.drow[di] = j;
-        w.rmap[j] = -1;
       }
+      if (j < n) w.rmap[j] = kept ? ck + ek : -1;
+      ck += tk;
+      cd += td;
+      cs += ts;
     }
-    ck += tk;
-    cs += tk;
-    cd += min(DNT, n - base) - tk;
-  }
-  for (int base = 0; !singles && base < n; base += DNT) {
-    const int j = base + tid;
-    int kept = 0, defl = 0, segst = 0;
-    int t = -1, g = -1, m = 1, pos = 0;
-    if (j < n) {
-      t = w.rmap[j];
-      if (t < 0) {
-        defl = 1;
-      } else {
-        g = w.grp_id[t];
-        m = w.g_m[g];
-        pos = t - w.g_first[g];
-        kept = (m == 1) || (pos < w.g_r[g]);
-        defl = !kept;
-        segst = kept && (pos == 0);
-      }
-    }
-    int tk, td, ts;
-    const int ek = block_excl_scan<DNT>(kept, shi, &tk);
-    const int ed = block_excl_scan<DNT>(defl, shi, &td);
-    const int es = block_excl_scan<DNT>(segst, shi, &ts);
-    if (kept) {
-      const int ri = ck + ek;
-      const int sid = cs + es + segst - 1;
-      w.rd[ri] = (m == 1) ? lam[j] : w.g_val[g];
-#pragma unroll
-      for (int c = 0; c < K; ++c)
-        w.ru[(size_t)ri * K + c] = (m == 1) ? w.U[(size_t)j * K + c] : w.urot[(size_t)t * K + c];
-      w.rrow[ri] = j;
-      w.row_seg[ri] = sid;
-      if (segst) {
-        w.seg_start[sid] = ri;
-        w.seg_r[sid] = (m == 1) ? 1 : w.g_r[g];
-      }
-    }
-    if (defl) {
-      const int di = cd + ed;
-      w.dval[di] = lam[j];
-      w.drow[di] = j;
-    }
-    if (j < n) w.rmap[j] = kept ? ck + ek : -1;
-    ck += tk;
-    cd += td;
-    cs += ts;
-  }
+  }  // !plain
   const double t2 = block_sum<DNT>(tiny2 + rem2, shd);
   spread = block_max<DNT>(spread, shd);
   if (tid == 0) {
