@@ -271,7 +271,7 @@ __device__ __forceinline__ GemmDescG ff_desc(const double* A, int lda, const dou
 // One block: near rows of every column block, the path decision, nodes,
 // descriptors and prefixes.
 __global__ __launch_bounds__(256) void ff_plan_kernel(Work w, FarField f) {
-  __shared__ int s_ok, s_full;
+  __shared__ int s_ok, s_full, s_lastpos;
   __shared__ int s_sl[FF_MAXNB];     // k-slices of each column block's product
   __shared__ short s_inv[FF_MAXNB];  // column block of each launch position
   // the intervals, read many times by the near-row searches
@@ -372,6 +372,7 @@ __global__ __launch_bounds__(256) void ff_plan_kernel(Work w, FarField f) {
     int pos = 0;
     for (int J = 0; J < nb; ++J) pos += (s_sl[J] > mine || (s_sl[J] == mine && J < I)) ? 1 : 0;
     s_inv[pos] = (short)I;
+    if (I == nb - 1) s_lastpos = pos;
     GemmSegDesc& g = f.seg[pos];  // written in place
     int ns = 0, sl = 0;
     bool vec = !(n & 1) && !(kpc & 1);
@@ -410,20 +411,14 @@ __global__ __launch_bounds__(256) void ff_plan_kernel(Work w, FarField f) {
     g.nseg = ns;
   }
   __syncthreads();
+  // tile offsets: P2M's are equal per row block; every column block has
+  // ff_tiles(FF_B) column tiles but the last, which may have more
+  const int tm = ff_tiles(n), pt = ff_ptiles(n) * ff_ptiles(kpr);
+  const int extra = ff_tiles(ff_bsize(n, nb, nb - 1, FF_B)) - ff_tiles(FF_B);
+  for (int h = threadIdx.x; h <= nr; h += 256) f.prefix[h] = h * pt;
+  for (int q = threadIdx.x; q <= nb; q += 256)  // before the q-th product launched
+    f.prefix[(nr + 1) + q] = tm * (ff_tiles(FF_B) * q + (s_lastpos < q ? extra : 0));
   if (threadIdx.x == 0) {
-    const int tm = ff_tiles(n);
-    int c = 0;
-    for (int h = 0; h < nr; ++h) {
-      f.prefix[h] = c;
-      c += ff_ptiles(n) * ff_ptiles(kpr);
-    }
-    f.prefix[nr] = c;
-    int a = 0;
-    for (int I = 0; I < nb; ++I) {
-      f.prefix[(nr + 1) + I] = a;  // the I-th product launched
-      a += tm * ff_tiles(ff_bsize(n, nb, s_inv[I], FF_B));
-    }
-    f.prefix[(nr + 1) + nb] = a;
     f.flags[0] = ok ? 0 : 1;                                             // far path skipped
     f.flags[1] = (ok || __builtin_nontemporal_load(&w.st->status) != 0) ? 1 : 0;  // dense skipped
   }
